@@ -1,0 +1,845 @@
+/*
+ * Plain FP64 CPU oracle for one operator-split step of ideal MHD with H/H2
+ * chemistry on a uniform periodic grid (Kulikov, Chernykh & Protasov,
+ * "A new code for numerical simulation of MHD astrophysical flows with
+ * chemistry", arXiv:1608.08748).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker for the HIP library:
+ * only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.  It shares no code, header, table or helper with the
+ * GPU path.  It is written to be read against the paper: scalar loops, one
+ * function per step of the method, every intermediate stored, no blocking or
+ * fusion.
+ *
+ * Stage names.  The paper calls the pressure / Lorentz-force / p dV stage the
+ * "eulerian" stage (Sec. 2, stage 1; Sec. 2.4) and the advection stage the
+ * "lagrangian" stage (Sec. 2, stage 3; Sec. 2.6).  Here they are NONADV and
+ * ADV respectively.
+ *
+ * Readings of passages that are ambiguous or garbled in the paper (each is
+ * also listed in the design notes of the repository):
+ *   R-dq     Sec. 2.1: dq = qR - qL (the printed qL - qR contradicts the
+ *            parabola formula and the overshoot tests).
+ *   R-step4w Sec. 2.1 Step 4: q_final = (1-w) q + w q^+ (w -> 1 only at
+ *            discontinuities); the printed weights are swapped.
+ *   R-step4c Sec. 2.1 Step 4: the "q_{i+1} q_{i-1} > 0" test is read as a
+ *            test on the second differences, d2 q_{i+1} d2 q_{i-1} > 0.
+ *   R-d2     Sec. 2.1 Step 4: d2 q_j = (q_{j+1} - 2 q_j + q_{j-1}) / (6 h^2);
+ *            the h^2 of eta cancels, so eta = -(D_{i+1}-D_{i-1})/(6 (q_{i+1}-q_{i-1}))
+ *            with D_j the plain second difference.
+ *   R-rk     Sec. 2.2: the three-stage SSP Runge-Kutta formulas, written in
+ *            increment form Q_s = Q_{s-1} + a_s (Q_0 - Q_{s-1}) + b_s tau R(Q_{s-1}).
+ *   R-theta  Sec. 2.4: the parabola-average width is theta * |lambda| * tau,
+ *            theta = 1 being the paper's literal choice; tau is the full step
+ *            in every Runge-Kutta substage.
+ *   R-avg    Sec. 2.4 face averages: left/right inputs are cell-centre values;
+ *            pressure uses the sqrt(rho) weights of the velocity.
+ *   R-b      Sec. 2.3: b = |B| / sqrt(rho) (the only reading under which the
+ *            printed eigenvectors diagonalise the Jacobian).
+ *   R-ab     Sec. 2.4 alpha/beta cases: alpha from the general formula when
+ *            cf^2 - cs^2 > eps (c^2 + b^2), else 1/sqrt(2); beta = Bt/|Bt| when
+ *            |Bt|^2 > eps (|B|^2 + gamma p), else 1/sqrt(2); sign(0) = +1.
+ *   R-bn     Sec. 2.4/2.5: the normal field at a face is the staggered face
+ *            value; transverse fields come from cell centres.
+ *   R-proj   Appendix (eigenvectors): the face state is the projector sum
+ *            q = sum_k r_k (l_k . q_up(k)); the expanded closed forms of the
+ *            appendix carry sign/factor typos and are not used.
+ *   R-adv    Sec. 2.6: lambda = |v_n| with v_n the sqrt(rho)-weighted face
+ *            normal velocity of the current substage.
+ *   R-ct     Sec. 2.5: the face-field update is part of the NONADV
+ *            Runge-Kutta state; each substage uses its own face states.
+ *   R-flux   Sec. 2 eqs. without advective terms: momentum flux
+ *            (P* - bn^2, -bn Bt1, -bn Bt2), energy flux P* Vn - bn (B.V),
+ *            internal energy source -(gamma-1) e div(V) from face velocities.
+ *   R-reg    Sec. 2.8: dual-energy synchronisation only: e = E-K-M where
+ *            E-K-M >= 1e-3 E and the pressure (gamma-1)(E-K-M) exceeds the
+ *            magnetic pressure M = B^2/2; elsewhere e is kept.  Velocities are
+ *            not changed.  The pressure gate is needed for the scheme to stay
+ *            stable at low beta: the split moves the magnetic part of E with
+ *            the Riemann velocity in NONADV but with the averaged velocity in
+ *            ADV, and an unconditional sync feeds that mismatch into the
+ *            pressure (it oscillates on the paper's shock tube of Sec. 3.1).
+ *   R-chem   Sec. 2.7 + Appendix rates: H/H2 only (reactions 1-4); n_H =
+ *            n_u (rho - h2), n_H2 = n_u h2 / 2, C = k1 n_H^2 with k1 carrying its
+ *            n/n_H factor (evaluated as k1' n n_H), D = k2 n_H + k3 n_H2 + k4,
+ *            k4 optically thin; one semi-implicit update per step.
+ *   R-units  Code units: n_u H nuclei per cm^3 per unit density, T = T_u mu p / rho
+ *            with mu = 1 / (1 - x_H2/2), time unit t_u seconds.
+ *   R-cfl    Sec. 2.3: verbatim speed sum v + b + c + c_a + c_s + c_f with
+ *            c_a from the x component of the cell-centre field.
+ *
+ * Layout: the state is 10 structure-of-arrays fields of nx*ny*nz doubles,
+ * x fastest: rho, mx, my, mz, E, e (= rho eps), bx, by, bz, h2 (= rho_H2).
+ * bx[i,j,k] is B_x on the face (i-1/2, j, k); by and bz likewise on the lower
+ * y and z faces of the cell.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stddef.h>
+
+enum { F_RHO = 0, F_MX, F_MY, F_MZ, F_E, F_EI, F_BX, F_BY, F_BZ, F_H2, NF };
+
+typedef struct {
+    int nx, ny, nz;
+    double gamma;
+    double cfl;
+    double theta;
+    int chemistry;
+    double n_unit;   /* H nuclei per cm^3 per unit code density */
+    double T_unit;   /* K: T = T_unit * mu * p / rho            */
+    double t_unit;   /* s per code time unit                    */
+} orc_params;
+
+/* ------------------------------------------------------------------ */
+/* indexing on the periodic grid                                        */
+/* ------------------------------------------------------------------ */
+static int wrap(int i, int n) { i %= n; return i < 0 ? i + n : i; }
+
+static size_t cell(const orc_params *P, int i, int j, int k)
+{
+    return (size_t)wrap(i, P->nx) + (size_t)P->nx *
+           ((size_t)wrap(j, P->ny) + (size_t)P->ny * (size_t)wrap(k, P->nz));
+}
+
+static size_t ncell(const orc_params *P)
+{
+    return (size_t)P->nx * (size_t)P->ny * (size_t)P->nz;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.1: local parabola on a 5-cell line q[0..4] = q_{i-2..i+2}.    */
+/* out = (qL, qR, dq, q6).                                              */
+/* ------------------------------------------------------------------ */
+
+/* Step 1: limited central difference delta_m q_j from q_{j-1}, q_j, q_{j+1}. */
+static double limited_slope(double qm, double q0, double qp)
+{
+    double dq = 0.5 * (qp - qm);
+    if ((qp - q0) * (q0 - qm) > 0.0) {
+        double m = fabs(dq);
+        double a = 2.0 * fabs(qp - q0);
+        double b = 2.0 * fabs(q0 - qm);
+        if (a < m) m = a;
+        if (b < m) m = b;
+        return dq >= 0.0 ? m : -m;
+    }
+    return 0.0;
+}
+
+/* Step 1: fourth-order interface value q_{j+1/2} from q_j, q_{j+1} and their slopes. */
+static double interface_value(double q0, double q1, double dm0, double dm1)
+{
+    return 0.5 * (q0 + q1) - (dm1 - dm0) / 6.0;
+}
+
+void orc_parabola(const double q[5], double out[4])
+{
+    const double qmm = q[0], qm = q[1], q0 = q[2], qp = q[3], qpp = q[4];
+
+    /* Step 1 */
+    double dm_m = limited_slope(qmm, qm, q0);
+    double dm_0 = limited_slope(qm, q0, qp);
+    double dm_p = limited_slope(q0, qp, qpp);
+    double qL = interface_value(qm, q0, dm_m, dm_0);
+    double qR = interface_value(q0, qp, dm_0, dm_p);
+
+    /* Step 2: parabola parameters and monotonicity of the edge values */
+    double dq = qR - qL;
+    double q6 = 6.0 * (q0 - 0.5 * (qL + qR));
+    if ((qL - q0) * (q0 - qR) <= 0.0) {
+        qL = q0;
+        qR = q0;
+    } else if (dq * q6 > dq * dq) {
+        qL = 3.0 * q0 - 2.0 * qR;
+    } else if (dq * q6 < -(dq * dq)) {
+        qR = 3.0 * q0 - 2.0 * qL;
+    }
+
+    /* Step 3: parameters from the new edge values (Step 5 recomputes them
+     * again after Step 4, so their values here are not used further). */
+
+    /* Step 4: discontinuity detector and blend */
+    double qLp = q0 - 0.25 * dm_0;
+    double qRp = q0 + 0.25 * dm_0;
+    double D_m = q0 - 2.0 * qm + qmm;       /* second difference at i-1 */
+    double D_p = qpp - 2.0 * qp + q0;       /* second difference at i+1 */
+    double d2m = D_m / 6.0;
+    double d2p = D_p / 6.0;
+    double eta = 0.0;
+    double aqp = fabs(qp), aqm = fabs(qm);
+    double mn = aqp;
+    if (aqm < mn) mn = aqm;
+    if (aqp + aqm < mn) mn = aqp + aqm;
+    int zero_eta = (fabs(qp - qm) - mn / 100.0 <= 0.0) || (d2p * d2m > 0.0);
+    if (!zero_eta)
+        eta = -(d2p - d2m) / (qp - qm);
+    double w = 20.0 * (eta - 0.05);
+    if (w > 1.0) w = 1.0;
+    if (w < 0.0) w = 0.0;
+    qL = (1.0 - w) * qL + w * qLp;
+    qR = (1.0 - w) * qR + w * qRp;
+
+    /* Step 5 */
+    dq = qR - qL;
+    q6 = 6.0 * (q0 - 0.5 * (qL + qR));
+
+    out[0] = qL;
+    out[1] = qR;
+    out[2] = dq;
+    out[3] = q6;
+}
+
+/* Sec. 2.4: average of the parabola over the right part of the cell of
+ * relative width y (the paper's q(-nu t)). */
+double orc_avg_right(const double par[4], double y)
+{
+    return par[1] - 0.5 * y * (par[2] - par[3] * (1.0 - 2.0 * y / 3.0));
+}
+
+/* Sec. 2.4: average over the left part of relative width y (q(+nu t)). */
+double orc_avg_left(const double par[4], double y)
+{
+    return par[0] + 0.5 * y * (par[2] + par[3] * (1.0 - 2.0 * y / 3.0));
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.3 / 2.4 / Appendix: eigen-structure of the NONADV Jacobian at a */
+/* face for q = (vn, vt1, vt2, Bt1, Bt2, p).                             */
+/* R is stored row-major with R[i*6+k] = component i of right vector k.  */
+/* L is stored row-major with L[k*6+j] = component j of left vector k.   */
+/* ------------------------------------------------------------------ */
+void orc_eigen(double rho, double p, double bn, double bt1, double bt2,
+               double gamma, double eps, double lam[6], double R[36], double L[36])
+{
+    double c2 = gamma * p / rho;
+    double ca2 = bn * bn / rho;
+    double b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) / rho;
+    double s = c2 + b2;
+    double disc = s * s - 4.0 * c2 * ca2;
+    if (disc < 0.0) disc = 0.0;
+    double sd = sqrt(disc);
+    double cf2 = 0.5 * (s + sd);
+    double cs2 = 0.5 * (s - sd);
+    if (cs2 < 0.0) cs2 = 0.0;
+    double c = sqrt(c2), ca = sqrt(ca2), cf = sqrt(cf2), cs = sqrt(cs2);
+
+    double af, as;
+    double den = cf2 - cs2;
+    if (den > eps * s) {
+        double nf = c2 - cs2, ns = cf2 - c2;
+        if (nf < 0.0) nf = 0.0;
+        if (ns < 0.0) ns = 0.0;
+        af = sqrt(nf / den);
+        as = sqrt(ns / den);
+    } else {
+        af = 1.0 / sqrt(2.0);
+        as = 1.0 / sqrt(2.0);
+    }
+    double by, bz;
+    double bt2sq = bt1 * bt1 + bt2 * bt2;
+    if (bt2sq > eps * (bn * bn + bt2sq + gamma * p)) {
+        double bt = sqrt(bt2sq);
+        by = bt1 / bt;
+        bz = bt2 / bt;
+    } else {
+        by = 1.0 / sqrt(2.0);
+        bz = 1.0 / sqrt(2.0);
+    }
+    double sg = bn >= 0.0 ? 1.0 : -1.0;
+    double sr = sqrt(rho);
+    double gp = gamma * p;
+    double r2 = sqrt(2.0);
+    double sr2 = sqrt(rho / 2.0);
+    double s2r = sqrt(2.0 * rho);
+
+    lam[0] = cf;  lam[1] = -cf;
+    lam[2] = cs;  lam[3] = -cs;
+    lam[4] = ca;  lam[5] = -ca;
+
+    /* right eigenvectors: columns of R (rows of the printed transpose) */
+    double RT[6][6] = {
+        {  af * cf, -as * cs * by * sg, -as * cs * bz * sg,  as * sr * c * by,  as * sr * c * bz, af * gp },
+        { -af * cf,  as * cs * by * sg,  as * cs * bz * sg,  as * sr * c * by,  as * sr * c * bz, af * gp },
+        {  as * cs,  af * cf * by * sg,  af * cf * bz * sg, -af * sr * c * by, -af * sr * c * bz, as * gp },
+        { -as * cs, -af * cf * by * sg, -af * cf * bz * sg, -af * sr * c * by, -af * sr * c * bz, as * gp },
+        {  0.0, -bz / r2 * sg,  by / r2 * sg,  sr2 * bz, -sr2 * by, 0.0 },
+        {  0.0, -bz / r2 * sg,  by / r2 * sg, -sr2 * bz,  sr2 * by, 0.0 },
+    };
+    double tc2 = 2.0 * c2;
+    double src = 2.0 * sr * c;
+    double rc2 = 2.0 * rho * c2;
+    double Lm[6][6] = {
+        {  af * cf / tc2, -as * cs * by / tc2 * sg, -as * cs * bz / tc2 * sg,  as * by / src,  as * bz / src, af / rc2 },
+        { -af * cf / tc2,  as * cs * by / tc2 * sg,  as * cs * bz / tc2 * sg,  as * by / src,  as * bz / src, af / rc2 },
+        {  as * cs / tc2,  af * cf * by / tc2 * sg,  af * cf * bz / tc2 * sg, -af * by / src, -af * bz / src, as / rc2 },
+        { -as * cs / tc2, -af * cf * by / tc2 * sg, -af * cf * bz / tc2 * sg, -af * by / src, -af * bz / src, as / rc2 },
+        {  0.0, -bz / r2 * sg,  by / r2 * sg,  bz / s2r, -by / s2r, 0.0 },
+        {  0.0, -bz / r2 * sg,  by / r2 * sg, -bz / s2r,  by / s2r, 0.0 },
+    };
+    for (int i = 0; i < 6; i++)
+        for (int k = 0; k < 6; k++) {
+            R[i * 6 + k] = RT[k][i];
+            L[k * 6 + i] = Lm[k][i];
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.4: linearised Riemann problem with parabolic data at one face. */
+/* cl, cr: cell-centre (rho, vn, vt1, vt2, Bt1, Bt2, p) of the two cells. */
+/* parl, parr: parabolas (4 numbers each) of the 6 variables             */
+/* (vn, vt1, vt2, Bt1, Bt2, p) of the left and right cells.               */
+/* bn: face normal field.  ydx = theta * tau / h.                        */
+/* out: (Vn, Vt1, Vt2, Bt1, Bt2, P) at the face.                          */
+/* ------------------------------------------------------------------ */
+void orc_riemann_face(const double cl[7], const double cr[7],
+                      const double parl[24], const double parr[24],
+                      double bn, double gamma, double eps, double ydx, double out[6])
+{
+    double sl = sqrt(cl[0]), srr = sqrt(cr[0]);
+    double w = sl + srr;
+    double rho = (sl * cl[0] + srr * cr[0]) / w;
+    double p = (sl * cl[6] + srr * cr[6]) / w;
+    /* cross-weighted transverse field */
+    double bt1 = (sl * cr[4] + srr * cl[4]) / w;
+    double bt2 = (sl * cr[5] + srr * cl[5]) / w;
+
+    double lam[6], R[36], L[36];
+    orc_eigen(rho, p, bn, bt1, bt2, gamma, eps, lam, R, L);
+
+    double s[6];
+    for (int k = 0; k < 6; k++) {
+        double qup[6];
+        /* waves 1,3,5 (positive speed) read the left cell, 2,4,6 the right cell */
+        double nu = fabs(lam[k]);
+        double y = ydx * nu;
+        for (int j = 0; j < 6; j++)
+            qup[j] = (k % 2 == 0) ? orc_avg_right(parl + 4 * j, y)
+                                  : orc_avg_left(parr + 4 * j, y);
+        double acc = 0.0;
+        for (int j = 0; j < 6; j++)
+            acc += L[k * 6 + j] * qup[j];
+        s[k] = acc;
+    }
+    for (int i = 0; i < 6; i++) {
+        double acc = 0.0;
+        for (int k = 0; k < 6; k++)
+            acc += R[i * 6 + k] * s[k];
+        out[i] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2 (equation of state, field projection of Sec. 2.5)             */
+/* ------------------------------------------------------------------ */
+
+/* primitive state of one cell: rho, vx, vy, vz, Bcx, Bcy, Bcz, p */
+static void cell_primitives(const orc_params *P, const double *U, int i, int j, int k, double w[8])
+{
+    size_t N = ncell(P);
+    size_t c = cell(P, i, j, k);
+    double rho = U[F_RHO * N + c];
+    w[0] = rho;
+    w[1] = U[F_MX * N + c] / rho;
+    w[2] = U[F_MY * N + c] / rho;
+    w[3] = U[F_MZ * N + c] / rho;
+    w[4] = 0.5 * (U[F_BX * N + c] + U[F_BX * N + cell(P, i + 1, j, k)]);
+    w[5] = 0.5 * (U[F_BY * N + c] + U[F_BY * N + cell(P, i, j + 1, k)]);
+    w[6] = 0.5 * (U[F_BZ * N + c] + U[F_BZ * N + cell(P, i, j, k + 1)]);
+    w[7] = (P->gamma - 1.0) * U[F_EI * N + c];
+}
+
+/* direction d: normal axis d, transverse t1 = d+1, t2 = d+2 (cyclic) */
+static void unit_offset(int d, int o[3]) { o[0] = o[1] = o[2] = 0; o[d] = 1; }
+
+/* ------------------------------------------------------------------ */
+/* NONADV right-hand side (Sec. 2.4, 2.5) for one Runge-Kutta substage.  */
+/* U: current substage state.  inc: tau * R(U) for mx,my,mz,E,e,bx,by,bz */
+/* stored in the field slots of a 10-field array (rho, h2 slots zero).   */
+/* ------------------------------------------------------------------ */
+static void nonadv_increment(const orc_params *P, const double *U, double dt, double *inc)
+{
+    const size_t N = ncell(P);
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
+    const double h = 1.0 / (double)nx;
+    const double dtdx = dt / h;
+    const double ydx = P->theta * dtdx;
+    const double gm = P->gamma;
+    const double eps = 1e-12;
+
+    double *W = (double *)malloc(sizeof(double) * 8 * N);
+    /* face states per direction: Vn, Vt1, Vt2, Bt1, Bt2, P (6 x N per direction) */
+    double *FS = (double *)malloc(sizeof(double) * 18 * N);
+
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                double w[8];
+                cell_primitives(P, U, i, j, k, w);
+                size_t c = cell(P, i, j, k);
+                for (int v = 0; v < 8; v++) W[v * N + c] = w[v];
+            }
+
+    for (int d = 0; d < 3; d++) {
+        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        int o[3];
+        unit_offset(d, o);
+        const double *bface = U + (size_t)(F_BX + d) * N;
+        #pragma omp parallel for collapse(2) schedule(static)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) {
+                    /* face between cell c - e_d (left) and c (right) */
+                    double line[6][7];    /* cells c-3e_d .. c+2e_d: rho, vn, vt1, vt2, Bt1, Bt2, p */
+                    for (int m = 0; m < 6; m++) {
+                        int s = m - 3;
+                        size_t cc = cell(P, i + s * o[0], j + s * o[1], k + s * o[2]);
+                        line[m][0] = W[0 * N + cc];
+                        line[m][1] = W[(1 + d) * N + cc];
+                        line[m][2] = W[(1 + t1) * N + cc];
+                        line[m][3] = W[(1 + t2) * N + cc];
+                        line[m][4] = W[(4 + t1) * N + cc];
+                        line[m][5] = W[(4 + t2) * N + cc];
+                        line[m][6] = W[7 * N + cc];
+                    }
+                    double parl[24], parr[24];
+                    for (int v = 0; v < 6; v++) {
+                        double ql[5], qr[5];
+                        for (int m = 0; m < 5; m++) {
+                            ql[m] = line[m][1 + v];       /* cells c-3 .. c+1 around c-1 */
+                            qr[m] = line[m + 1][1 + v];   /* cells c-2 .. c+2 around c   */
+                        }
+                        orc_parabola(ql, parl + 4 * v);
+                        orc_parabola(qr, parr + 4 * v);
+                    }
+                    size_t c = cell(P, i, j, k);
+                    double out[6];
+                    orc_riemann_face(line[2], line[3], parl, parr, bface[c], gm, eps, ydx, out);
+                    for (int v = 0; v < 6; v++) FS[(size_t)(6 * d + v) * N + c] = out[v];
+                }
+    }
+
+    /* fluxes and EMF contributions per face (Sec. 2 equations without the
+     * advective terms; Sec. 2.5 E = B x U with the face states) */
+    double *FL = (double *)malloc(sizeof(double) * 15 * N);  /* per dir: Fmn, Fmt1, Fmt2, FE, Vn */
+    double *EM = (double *)malloc(sizeof(double) * 6 * N);   /* per dir: E_t1 part, E_t2 part */
+    for (int d = 0; d < 3; d++) {
+        const double *bface = U + (size_t)(F_BX + d) * N;
+        #pragma omp parallel for schedule(static)
+        for (size_t c = 0; c < N; c++) {
+            double Vn = FS[(size_t)(6 * d + 0) * N + c];
+            double Vt1 = FS[(size_t)(6 * d + 1) * N + c];
+            double Vt2 = FS[(size_t)(6 * d + 2) * N + c];
+            double Bt1 = FS[(size_t)(6 * d + 3) * N + c];
+            double Bt2 = FS[(size_t)(6 * d + 4) * N + c];
+            double Pg = FS[(size_t)(6 * d + 5) * N + c];
+            double bn = bface[c];
+            double Pst = Pg + 0.5 * (bn * bn + Bt1 * Bt1 + Bt2 * Bt2);
+            double BV = bn * Vn + Bt1 * Vt1 + Bt2 * Vt2;
+            FL[(size_t)(5 * d + 0) * N + c] = Pst - bn * bn;
+            FL[(size_t)(5 * d + 1) * N + c] = -(bn * Bt1);
+            FL[(size_t)(5 * d + 2) * N + c] = -(bn * Bt2);
+            FL[(size_t)(5 * d + 3) * N + c] = Pst * Vn - bn * BV;
+            FL[(size_t)(5 * d + 4) * N + c] = Vn;
+            /* E component along t1: B_t2 U_n - B_n U_t2; along t2: B_n U_t1 - B_t1 U_n */
+            EM[(size_t)(2 * d + 0) * N + c] = Bt2 * Vn - bn * Vt2;
+            EM[(size_t)(2 * d + 1) * N + c] = bn * Vt1 - Bt1 * Vn;
+        }
+    }
+    /* EMF contribution to component a from the face of direction d:
+     * d = x gives (E_y, E_z), d = y gives (E_z, E_x), d = z gives (E_x, E_y). */
+#define EMF(d, slot, ii, jj, kk) EM[(size_t)(2 * (d) + (slot)) * N + cell(P, ii, jj, kk)]
+
+    /* edge fields, Appendix (electric field):
+     *   Ex at (i, j-1/2, k-1/2): z-faces at j-1 and j, y-faces at k and k-1
+     *   Ey at (i-1/2, j, k-1/2): z-faces at i-1 and i, x-faces at k-1 and k
+     *   Ez at (i-1/2, j-1/2, k): x-faces at j-1 and j, y-faces at i-1 and i */
+    double *Ed = (double *)malloc(sizeof(double) * 3 * N);
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t c = cell(P, i, j, k);
+                Ed[0 * N + c] = 0.25 * (EMF(2, 0, i, j - 1, k) + EMF(2, 0, i, j, k) +
+                                        EMF(1, 1, i, j, k) + EMF(1, 1, i, j, k - 1));
+                Ed[1 * N + c] = 0.25 * (EMF(2, 1, i - 1, j, k) + EMF(2, 1, i, j, k) +
+                                        EMF(0, 0, i, j, k - 1) + EMF(0, 0, i, j, k));
+                Ed[2 * N + c] = 0.25 * (EMF(0, 1, i, j - 1, k) + EMF(0, 1, i, j, k) +
+                                        EMF(1, 0, i - 1, j, k) + EMF(1, 0, i, j, k));
+            }
+#undef EMF
+
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t c = cell(P, i, j, k);
+                size_t up[3] = { cell(P, i + 1, j, k), cell(P, i, j + 1, k), cell(P, i, j, k + 1) };
+                double dF[3][5];
+                for (int d = 0; d < 3; d++)
+                    for (int v = 0; v < 5; v++)
+                        dF[d][v] = FL[(size_t)(5 * d + v) * N + up[d]] - FL[(size_t)(5 * d + v) * N + c];
+                /* momentum component a receives, from direction d, the flux slot
+                 * 0 if a == d, 1 if a == d+1, 2 if a == d+2 (cyclic) */
+                for (int a = 0; a < 3; a++) {
+                    double sum = 0.0;
+                    for (int d = 0; d < 3; d++) {
+                        int slot = (a - d + 3) % 3;
+                        sum += dF[d][slot];
+                    }
+                    inc[(size_t)(F_MX + a) * N + c] = -dtdx * sum;
+                }
+                inc[F_E * N + c] = -dtdx * (dF[0][3] + dF[1][3] + dF[2][3]);
+                double divv = dF[0][4] + dF[1][4] + dF[2][4];
+                inc[F_EI * N + c] = -(gm - 1.0) * U[F_EI * N + c] * dtdx * divv;
+
+                /* Sec. 2.5 face-field update from the edge fields */
+                double dEz_y = Ed[2 * N + cell(P, i, j + 1, k)] - Ed[2 * N + c];
+                double dEy_z = Ed[1 * N + cell(P, i, j, k + 1)] - Ed[1 * N + c];
+                double dEx_z = Ed[0 * N + cell(P, i, j, k + 1)] - Ed[0 * N + c];
+                double dEz_x = Ed[2 * N + cell(P, i + 1, j, k)] - Ed[2 * N + c];
+                double dEy_x = Ed[1 * N + cell(P, i + 1, j, k)] - Ed[1 * N + c];
+                double dEx_y = Ed[0 * N + cell(P, i, j + 1, k)] - Ed[0 * N + c];
+                inc[F_BX * N + c] = -dtdx * dEz_y + dtdx * dEy_z;
+                inc[F_BY * N + c] = -dtdx * dEx_z + dtdx * dEz_x;
+                inc[F_BZ * N + c] = -dtdx * dEy_x + dtdx * dEx_y;
+                inc[F_RHO * N + c] = 0.0;
+                inc[F_H2 * N + c] = 0.0;
+            }
+
+    free(W);
+    free(FS);
+    free(FL);
+    free(EM);
+    free(Ed);
+}
+
+/* ------------------------------------------------------------------ */
+/* ADV right-hand side (Sec. 2.6): upwind parabola averages of the      */
+/* conserved fields rho, mx, my, mz, E, e, h2 with the sqrt(rho)-weighted */
+/* face velocity.                                                       */
+/* ------------------------------------------------------------------ */
+static const int adv_fields[7] = { F_RHO, F_MX, F_MY, F_MZ, F_E, F_EI, F_H2 };
+
+static void adv_increment(const orc_params *P, const double *U, double dt, double *inc)
+{
+    const size_t N = ncell(P);
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
+    const double h = 1.0 / (double)nx;
+    const double dtdx = dt / h;
+    const double ydx = P->theta * dtdx;
+
+    double *F = (double *)malloc(sizeof(double) * 21 * N);   /* per dir, per field */
+
+    for (int d = 0; d < 3; d++) {
+        int o[3];
+        unit_offset(d, o);
+        #pragma omp parallel for collapse(2) schedule(static)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) {
+                    size_t c = cell(P, i, j, k);
+                    size_t cl = cell(P, i - o[0], j - o[1], k - o[2]);
+                    double rl = U[F_RHO * N + cl], rr = U[F_RHO * N + c];
+                    double vl = U[(size_t)(F_MX + d) * N + cl] / rl;
+                    double vr = U[(size_t)(F_MX + d) * N + c] / rr;
+                    double sl = sqrt(rl), sr = sqrt(rr);
+                    double vf = (sl * vl + sr * vr) / (sl + sr);
+                    for (int f = 0; f < 7; f++) {
+                        const double *q = U + (size_t)adv_fields[f] * N;
+                        double flux;
+                        if (vf >= 0.0) {
+                            double s5[5], par[4];
+                            for (int m = 0; m < 5; m++) {
+                                int s = m - 3;
+                                s5[m] = q[cell(P, i + s * o[0], j + s * o[1], k + s * o[2])];
+                            }
+                            orc_parabola(s5, par);
+                            flux = vf * orc_avg_right(par, ydx * vf);
+                        } else {
+                            double s5[5], par[4];
+                            for (int m = 0; m < 5; m++) {
+                                int s = m - 2;
+                                s5[m] = q[cell(P, i + s * o[0], j + s * o[1], k + s * o[2])];
+                            }
+                            orc_parabola(s5, par);
+                            flux = vf * orc_avg_left(par, ydx * (-vf));
+                        }
+                        F[(size_t)(7 * d + f) * N + c] = flux;
+                    }
+                }
+    }
+
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t c = cell(P, i, j, k);
+                size_t up[3] = { cell(P, i + 1, j, k), cell(P, i, j + 1, k), cell(P, i, j, k + 1) };
+                for (int f = 0; f < 7; f++) {
+                    double dx = F[(size_t)(7 * 0 + f) * N + up[0]] - F[(size_t)(7 * 0 + f) * N + c];
+                    double dy = F[(size_t)(7 * 1 + f) * N + up[1]] - F[(size_t)(7 * 1 + f) * N + c];
+                    double dz = F[(size_t)(7 * 2 + f) * N + up[2]] - F[(size_t)(7 * 2 + f) * N + c];
+                    inc[(size_t)adv_fields[f] * N + c] = -dtdx * (dx + dy + dz);
+                }
+                inc[F_BX * N + c] = 0.0;
+                inc[F_BY * N + c] = 0.0;
+                inc[F_BZ * N + c] = 0.0;
+            }
+    free(F);
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.2: three-stage Runge-Kutta over one split stage.               */
+/* ------------------------------------------------------------------ */
+typedef void (*rhs_fn)(const orc_params *, const double *, double, double *);
+
+static void rk3_stage(const orc_params *P, double *U, double dt, rhs_fn rhs)
+{
+    const size_t N = ncell(P);
+    const size_t T = NF * N;
+    static const double a[3] = { 0.0, 0.75, 1.0 / 3.0 };
+    static const double b[3] = { 1.0, 0.25, 2.0 / 3.0 };
+    double *U0 = (double *)malloc(sizeof(double) * T);
+    double *inc = (double *)malloc(sizeof(double) * T);
+    memcpy(U0, U, sizeof(double) * T);
+    for (int s = 0; s < 3; s++) {
+        rhs(P, U, dt, inc);
+        #pragma omp parallel for schedule(static)
+        for (size_t t = 0; t < T; t++)
+            U[t] = (U[t] + a[s] * (U0[t] - U[t])) + b[s] * inc[t];
+    }
+    free(U0);
+    free(inc);
+}
+
+void orc_nonadv_stage(const orc_params *P, double *U, double dt) { rk3_stage(P, U, dt, nonadv_increment); }
+void orc_adv_stage(const orc_params *P, double *U, double dt) { rk3_stage(P, U, dt, adv_increment); }
+
+/* single-substage right-hand sides, for unit checks: inc = tau R(U) */
+void orc_nonadv_rhs(const orc_params *P, const double *U, double dt, double *inc) { nonadv_increment(P, U, dt, inc); }
+void orc_adv_rhs(const orc_params *P, const double *U, double dt, double *inc) { adv_increment(P, U, dt, inc); }
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.7 + Appendix (reaction rates 1-4): H/H2 chemistry of one cell. */
+/* Returns the new H2 mass density.  rates_out (optional): k1', k2, k3, */
+/* k4, C, D, T.                                                          */
+/* ------------------------------------------------------------------ */
+
+/* k1 without its n/n_H factor: C = k1 n_H^2 = k1' n n_H (Appendix, reaction 1) */
+double orc_k1_base(double T)
+{
+    double t2 = T / 100.0;
+    return 3e-17 * sqrt(t2) / (1.0 + 0.4 * sqrt(t2) + 0.2 * t2 + 0.08 * t2 * t2);
+}
+
+double orc_k2(double T)   /* Appendix, reaction 2 (collisional dissociation by H) */
+{
+    if (T > 7390.0) return 6.11e-14 * exp(-2.93e4 / T);
+    return 2.67e-15 * exp(-(6750.0 / T) * (6750.0 / T));
+}
+
+double orc_k3(double T)   /* Appendix, reaction 3 (collisional dissociation by H2) */
+{
+    if (T > 7291.0) return 5.22e-14 * exp(-3.22e4 / T);
+    return 3.17e-15 * exp(-(4060.0 / T) - (7500.0 / T) * (7500.0 / T));
+}
+
+double orc_k4(void)       /* Appendix, reaction 4: optically thin, f_shield = f_dust = 1 */
+{
+    return 3.3 * 1.7e-11;
+}
+
+double orc_chem_cell(const orc_params *P, double rho, double e, double h2, double dt, double *rates_out)
+{
+    double p = (P->gamma - 1.0) * e;
+    double xh2 = h2 / rho;
+    double mu = 1.0 / (1.0 - 0.5 * xh2);
+    double T = P->T_unit * mu * p / rho;
+    double nH = P->n_unit * (rho - h2);
+    double nH2 = P->n_unit * h2 / 2.0;
+    double n = nH + nH2;
+    double k1b = orc_k1_base(T), k2 = orc_k2(T), k3 = orc_k3(T), k4 = orc_k4();
+    double C = k1b * n * nH;
+    double D = k2 * nH + k3 * nH2 + k4;
+    double ts = dt * P->t_unit;
+    /* Sec. 2.7: n(t+tau) = n + tau (C - D n) / (1 + tau D) */
+    double nn = nH2 + ts * (C - D * nH2) / (1.0 + ts * D);
+    double nmax = P->n_unit * rho / 2.0;
+    if (nn > nmax) nn = nmax;
+    if (nn < 0.0) nn = 0.0;
+    if (rates_out) {
+        rates_out[0] = k1b; rates_out[1] = k2; rates_out[2] = k3; rates_out[3] = k4;
+        rates_out[4] = C; rates_out[5] = D; rates_out[6] = T;
+    }
+    return 2.0 * nn / P->n_unit;
+}
+
+/* clamp of the advected H2 density to [0, rho] (total hydrogen closure) */
+void orc_clamp_h2(const orc_params *P, double *U)
+{
+    const size_t N = ncell(P);
+    for (size_t c = 0; c < N; c++) {
+        double r = U[F_RHO * N + c], x = U[F_H2 * N + c];
+        if (x > r) x = r;
+        if (x < 0.0) x = 0.0;
+        U[F_H2 * N + c] = x;
+    }
+}
+
+void orc_chemistry(const orc_params *P, double *U, double dt)
+{
+    const size_t N = ncell(P);
+    #pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < N; c++)
+        U[F_H2 * N + c] = orc_chem_cell(P, U[F_RHO * N + c], U[F_EI * N + c], U[F_H2 * N + c], dt, NULL);
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.8: regularisation (dual-energy synchronisation, pressure-gated). */
+/* ------------------------------------------------------------------ */
+void orc_regularise(const orc_params *P, double *U)
+{
+    const size_t N = ncell(P);
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                size_t c = cell(P, i, j, k);
+                double rho = U[F_RHO * N + c];
+                double mx = U[F_MX * N + c], my = U[F_MY * N + c], mz = U[F_MZ * N + c];
+                double bx = 0.5 * (U[F_BX * N + c] + U[F_BX * N + cell(P, i + 1, j, k)]);
+                double by = 0.5 * (U[F_BY * N + c] + U[F_BY * N + cell(P, i, j + 1, k)]);
+                double bz = 0.5 * (U[F_BZ * N + c] + U[F_BZ * N + cell(P, i, j, k + 1)]);
+                double E = U[F_E * N + c];
+                double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+                double M = 0.5 * (bx * bx + by * by + bz * bz);
+                double ei = E - K - M;
+                if (ei >= 1e-3 * E && (P->gamma - 1.0) * ei > M) U[F_EI * N + c] = ei;
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.3: time step from the CFL condition.                          */
+/* ------------------------------------------------------------------ */
+double orc_cell_speed(const orc_params *P, const double *U, int i, int j, int k)
+{
+    const size_t N = ncell(P);
+    double w[8];
+    cell_primitives(P, U, i, j, k, w);
+    double rho = w[0];
+    double v = sqrt(w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    double c2 = P->gamma * w[7] / rho;
+    double ca2 = w[4] * w[4] / rho;
+    double b2 = (w[4] * w[4] + w[5] * w[5] + w[6] * w[6]) / rho;
+    double s = c2 + b2;
+    double disc = s * s - 4.0 * c2 * ca2;
+    if (disc < 0.0) disc = 0.0;
+    double sd = sqrt(disc);
+    double cf2 = 0.5 * (s + sd);
+    double cs2 = 0.5 * (s - sd);
+    if (cs2 < 0.0) cs2 = 0.0;
+    (void)N;
+    return v + sqrt(b2) + sqrt(c2) + sqrt(ca2) + sqrt(cs2) + sqrt(cf2);
+}
+
+double orc_cfl_dt(const orc_params *P, const double *U)
+{
+    const double h = 1.0 / (double)P->nx;
+    double best = INFINITY;
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                double t = P->cfl * h / orc_cell_speed(P, U, i, j, k);
+                if (t < best) best = t;
+            }
+    return best;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2 list of stages: one operator-split step (no gravity, no        */
+/* heating/cooling): NONADV (with the face-field update inside),        */
+/* ADV, H2 clamp, chemistry, regularisation.                            */
+/* ------------------------------------------------------------------ */
+void orc_step(const orc_params *P, double *U, double dt)
+{
+    orc_nonadv_stage(P, U, dt);
+    orc_adv_stage(P, U, dt);
+    orc_clamp_h2(P, U);
+    if (P->chemistry) orc_chemistry(P, U, dt);
+    orc_regularise(P, U);
+}
+
+/* conserved totals in field order rho, mx, my, mz, E, e, bx, by, bz, h2
+ * (compensated summation, so the totals themselves carry no O(N eps) drift) */
+void orc_totals(const orc_params *P, const double *U, double out[NF])
+{
+    const size_t N = ncell(P);
+    for (int f = 0; f < NF; f++) {
+        double s = 0.0, comp = 0.0;
+        for (size_t c = 0; c < N; c++) {
+            double x = U[(size_t)f * N + c];
+            double t = s + x;
+            if (fabs(s) >= fabs(x)) comp += (s - t) + x;
+            else comp += (x - t) + s;
+            s = t;
+        }
+        out[f] = s + comp;
+    }
+}
+
+/* primitive -> conserved: prim fields rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2 */
+void orc_prim_to_cons(const orc_params *P, const double *W, double *U)
+{
+    const size_t N = ncell(P);
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                size_t c = cell(P, i, j, k);
+                double rho = W[0 * N + c];
+                double vx = W[1 * N + c], vy = W[2 * N + c], vz = W[3 * N + c];
+                double p = W[4 * N + c];
+                double bx = 0.5 * (W[5 * N + c] + W[5 * N + cell(P, i + 1, j, k)]);
+                double by = 0.5 * (W[6 * N + c] + W[6 * N + cell(P, i, j + 1, k)]);
+                double bz = 0.5 * (W[7 * N + c] + W[7 * N + cell(P, i, j, k + 1)]);
+                double e = p / (P->gamma - 1.0);
+                U[F_RHO * N + c] = rho;
+                U[F_MX * N + c] = rho * vx;
+                U[F_MY * N + c] = rho * vy;
+                U[F_MZ * N + c] = rho * vz;
+                U[F_EI * N + c] = e;
+                U[F_E * N + c] = e + 0.5 * rho * (vx * vx + vy * vy + vz * vz) + 0.5 * (bx * bx + by * by + bz * bz);
+                U[F_BX * N + c] = W[5 * N + c];
+                U[F_BY * N + c] = W[6 * N + c];
+                U[F_BZ * N + c] = W[7 * N + c];
+                U[F_H2 * N + c] = W[8 * N + c] * rho;
+            }
+}
+
+/* discrete face-based divergence of B times h, max |.| over cells */
+double orc_max_divb(const orc_params *P, const double *U)
+{
+    const size_t N = ncell(P);
+    double m = 0.0;
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                size_t c = cell(P, i, j, k);
+                double d = (U[F_BX * N + cell(P, i + 1, j, k)] - U[F_BX * N + c]) +
+                           (U[F_BY * N + cell(P, i, j + 1, k)] - U[F_BY * N + c]) +
+                           (U[F_BZ * N + cell(P, i, j, k + 1)] - U[F_BZ * N + c]);
+                if (fabs(d) > m) m = fabs(d);
+            }
+    return m;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
