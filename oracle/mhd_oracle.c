@@ -127,10 +127,10 @@ static double limited_slope(double qm, double q0, double qp)
     return 0.0;
 }
 
-/* Step 1: fourth-order interface value q_{j+1/2} from q_j, q_{j+1} and their slopes. */
+/* Step 1: fourth-order interface value q_{j+1/2} = 1/2 (q_j + q_{j+1}) - 1/6 (dm_{j+1} - dm_j). */
 static double interface_value(double q0, double q1, double dm0, double dm1)
 {
-    return 0.5 * (q0 + q1) - (dm1 - dm0) / 6.0;
+    return 0.5 * (q0 + q1) - (1.0 / 6.0) * (dm1 - dm0);
 }
 
 void orc_parabola(const double q[5], double out[4])
@@ -164,16 +164,15 @@ void orc_parabola(const double q[5], double out[4])
     double qRp = q0 + 0.25 * dm_0;
     double D_m = q0 - 2.0 * qm + qmm;       /* second difference at i-1 */
     double D_p = qpp - 2.0 * qp + q0;       /* second difference at i+1 */
-    double d2m = D_m / 6.0;
-    double d2p = D_p / 6.0;
     double eta = 0.0;
     double aqp = fabs(qp), aqm = fabs(qm);
     double mn = aqp;
     if (aqm < mn) mn = aqm;
     if (aqp + aqm < mn) mn = aqp + aqm;
-    int zero_eta = (fabs(qp - qm) - mn / 100.0 <= 0.0) || (d2p * d2m > 0.0);
+    /* d2 q_j = D_j / (6 h^2): the h^2 cancels in eta and the sign test is scale free */
+    int zero_eta = (fabs(qp - qm) - 0.01 * mn <= 0.0) || (D_p * D_m > 0.0);
     if (!zero_eta)
-        eta = -(d2p - d2m) / (qp - qm);
+        eta = -(D_p - D_m) / (6.0 * (qp - qm));
     double w = 20.0 * (eta - 0.05);
     if (w > 1.0) w = 1.0;
     if (w < 0.0) w = 0.0;
@@ -194,13 +193,13 @@ void orc_parabola(const double q[5], double out[4])
  * relative width y (the paper's q(-nu t)). */
 double orc_avg_right(const double par[4], double y)
 {
-    return par[1] - 0.5 * y * (par[2] - par[3] * (1.0 - 2.0 * y / 3.0));
+    return par[1] - 0.5 * y * (par[2] - par[3] * (1.0 - (2.0 / 3.0) * y));
 }
 
 /* Sec. 2.4: average over the left part of relative width y (q(+nu t)). */
 double orc_avg_left(const double par[4], double y)
 {
-    return par[0] + 0.5 * y * (par[2] + par[3] * (1.0 - 2.0 * y / 3.0));
+    return par[0] + 0.5 * y * (par[2] + par[3] * (1.0 - (2.0 / 3.0) * y));
 }
 
 /* ------------------------------------------------------------------ */
