@@ -1,0 +1,152 @@
+/*
+ * mhdchem: one operator-split time step of ideal MHD with H/H2 chemistry on a
+ * uniform periodic 3D grid, after Kulikov, Chernykh & Protasov (arXiv:1608.08748),
+ * on one AMD MI355X (gfx950).
+ *
+ * The step (Sec. 2, stages 1-4 and 6 of the paper's list; no gravity, no
+ * heating/cooling):
+ *   NONADV  pressure, Lorentz force and p dV work by a linearised Riemann
+ *           problem with local-parabola data at every face (Sec. 2.1, 2.4),
+ *           with the face-centred magnetic field updated from edge electric
+ *           fields inside the same Runge-Kutta stage (Sec. 2.5);
+ *   ADV     advection of rho, momentum, total and internal energy and H2
+ *           density by upwind parabola averages (Sec. 2.6);
+ *           each of the two stages is one three-stage SSP Runge-Kutta pass
+ *           (Sec. 2.2);
+ *   CHEM    semi-implicit H/H2 update per cell, reactions 1-4 (Sec. 2.7 and
+ *           the rate appendix), always in FP64;
+ *   REG     dual-energy regularisation (Sec. 2.8), always in FP64.
+ * The time step follows the CFL rule of Sec. 2.3.
+ *
+ * State (conserved, structure of arrays, x fastest, field order):
+ *   0 rho  1 mx  2 my  3 mz  4 E (total energy density incl. B^2/2)
+ *   5 e (internal energy density)  6 bx  7 by  8 bz  9 h2 (H2 mass density)
+ * bx[i,j,k] is B_x on the lower x face (i-1/2, j, k) of cell (i,j,k); by and bz
+ * likewise on the lower y and z faces.  Heaviside-Lorentz units (B^2/2 is the
+ * magnetic pressure).  Cells are cubes of edge h = 1 / n[0].
+ *
+ * Conventions for every entry point:
+ *   - return MHD_OK (0) or a negative status; no exception crosses the ABI;
+ *   - host buffers are owned by the caller and only read/written during the
+ *     call; device memory is the caller's workspace, borrowed for the box's
+ *     lifetime and never freed by the library; nothing on the step path
+ *     allocates device memory;
+ *   - all device work goes to the caller's stream in submission order;
+ *     mhd_step returns before the work finishes;
+ *   - faults found on the device (non-finite or non-positive density or
+ *     internal energy, a dt above the CFL bound) are latched in the workspace
+ *     and returned by the next synchronising call (mhd_cfl_dt,
+ *     mhd_conserved_totals, mhd_get_state) and stay latched until the next
+ *     mhd_init_state / mhd_set_state;
+ *   - one box is driven by one host thread at a time; distinct boxes are
+ *     independent.
+ */
+#ifndef MHDCHEM_H
+#define MHDCHEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MHD_OK = 0,
+    MHD_EINVAL = -1,     /* bad argument (dims, NULL, dt not finite or <= 0, ...) */
+    MHD_ENOMEM = -2,     /* workspace missing or smaller than mhd_workspace_bytes */
+    MHD_EDEVICE = -3,    /* a HIP runtime call failed                             */
+    MHD_ECFL = -4,       /* a step used dt above the CFL bound of its start state */
+    MHD_ENONPHYS = -5    /* non-finite or non-positive rho or e after a step       */
+};
+
+enum { MHD_FP64 = 0, MHD_FP32_MIXED = 1 };
+
+/* Stage selectors of mhd_debug_stage. */
+enum {
+    MHD_STAGE_NONADV = 1,    /* the NONADV Runge-Kutta stage only                   */
+    MHD_STAGE_ADV = 2,       /* the ADV Runge-Kutta stage only                      */
+    MHD_STAGE_TAIL = 3,      /* H2 clamp, chemistry (if enabled), regularisation    */
+    MHD_STAGE_NONADV_RHS = 4,/* one NONADV substage from the current state: writes  */
+                             /* tau R(U) into the state slots (rho, h2 slots zero)  */
+    MHD_STAGE_ADV_RHS = 5    /* one ADV substage: tau R(U) (face-field slots zero)  */
+};
+
+typedef struct {
+    int32_t n[3];            /* cells along x, y, z (periodic); each >= 1, product < 2^31 */
+    double gamma;            /* adiabatic index (5/3 in the configurations)             */
+    double cfl;              /* Courant number of Sec. 2.3 (paper 0.2)                  */
+    int32_t precision;       /* MHD_FP64 or MHD_FP32_MIXED (FP32 state and fluxes;      */
+                             /* chemistry, regularisation, CFL and totals in FP64)      */
+    double theta;            /* time coupling of the parabola averages: width           */
+                             /* theta*|lambda|*tau (1 = the paper, 0 = edge values)     */
+    int32_t chemistry;       /* 0 or 1                                                   */
+    double n_unit_cm3;       /* H nuclei per cm^3 per unit code density                 */
+    double T_unit_K;         /* T = T_unit_K * mu * p / rho, mu = 1/(1 - x_H2/2)         */
+    double t_unit_s;         /* seconds per code time unit                               */
+    void *stream;            /* hipStream_t of the caller; NULL = the null stream       */
+    void *workspace;         /* device memory, >= mhd_workspace_bytes, 256-byte aligned */
+    size_t workspace_bytes;
+} mhd_params;
+
+typedef struct mhd_box mhd_box;
+
+/* Device bytes the box needs for these parameters (three copies of the state
+ * for the Runge-Kutta stages, face scratch, reduction partials and flags).
+ * Host-only; returns 0 for invalid parameters. */
+size_t mhd_workspace_bytes(const mhd_params *p);
+
+/* Validate parameters and bind a box to the caller's workspace and stream.
+ * Host-only (no device call).  *out is owned by the caller until mhd_destroy. */
+int mhd_create(const mhd_params *p, mhd_box **out);
+
+/* Load a primitive state: host FP64, 9 fields of n[0]*n[1]*n[2] values, order
+ * rho, vx, vy, vz, p, bx_face, by_face, bz_face, x_h2 (H2 mass fraction).
+ * Converts to conserved form on the device (Sec. 2: rho E = e + rho v^2/2 +
+ * B^2/2 with cell-centre B the mean of the two faces, p = (gamma-1) e),
+ * computes the first CFL step, clears latched faults.  Synchronises. */
+int mhd_init_state(mhd_box *b, const double *prim);
+
+/* Load a conserved state (host FP64, the 10 fields above); clears faults and
+ * recomputes the CFL step.  Synchronises.  With mhd_get_state this is the
+ * checkpoint / resume pair (bitwise for MHD_FP64). */
+int mhd_set_state(mhd_box *b, const double *cons);
+
+/* Copy the current conserved state to host FP64 (10 fields).  Synchronises;
+ * returns a latched fault if any. */
+int mhd_get_state(mhd_box *b, double *cons_out);
+
+/* CFL time step of the current state (Sec. 2.3): min over cells of
+ * cfl*h / (|v| + b + c + c_a + c_s + c_f), b = |B|/sqrt(rho), c_a from B_x.
+ * Synchronises; returns a latched fault if any. */
+int mhd_cfl_dt(mhd_box *b, double *dt_out);
+
+/* Advance the state by dt: NONADV, ADV, H2 clamp to [0, rho], chemistry,
+ * regularisation; then the CFL step of the new state is computed on the
+ * device.  Asynchronous.  dt must be finite and > 0 (else MHD_EINVAL); a dt
+ * above the CFL bound of the start state latches MHD_ECFL. */
+int mhd_step(mhd_box *b, double dt);
+
+/* As mhd_step with the device-resident CFL step of the current state
+ * (no host round trip). */
+int mhd_step_cfl(mhd_box *b);
+
+/* FP64 sums over all cells of the 10 conserved fields (field order above;
+ * the face fields sum their face values).  Fixed-order tree reduction:
+ * repeatable bit for bit.  Synchronises; returns a latched fault if any. */
+int mhd_conserved_totals(mhd_box *b, double out[10]);
+
+/* Run one part of the step on the current state (stage selectors above),
+ * for per-stage parity checks.  Asynchronous. */
+int mhd_debug_stage(mhd_box *b, int stage, double dt);
+
+/* Release the box (not the workspace, not the stream). */
+int mhd_destroy(mhd_box *b);
+
+const char *mhd_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,195 @@
+"""Thin ctypes binding of libmhdchem.so (include/mhdchem.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides the device workspace and the stream.  Importing this module
+does not touch the GPU; creating a ``Box`` does (it allocates the workspace).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhdchem.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mhdchem.h")
+
+MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ECFL, MHD_ENONPHYS = 0, -1, -2, -3, -4, -5
+FP64, FP32_MIXED = 0, 1
+STAGE_NONADV, STAGE_ADV, STAGE_TAIL, STAGE_NONADV_RHS, STAGE_ADV_RHS = 1, 2, 3, 4, 5
+FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2")
+
+# chemistry unit map: 5 H nuclei per cm^3 per unit density, T_u = 5000 K,
+# t_u = L_u / v_u with L_u = 256 pc and v_u = sqrt(k_B T_u / m_H)
+_KB, _MH, _PC = 1.380649e-16, 1.6735575e-24, 3.0856775814913673e18
+DEFAULT_UNITS = (5.0, 5000.0, 256.0 * _PC / (_KB * 5000.0 / _MH) ** 0.5)
+
+
+class MhdParams(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("theta", ctypes.c_double),
+        ("chemistry", ctypes.c_int32),
+        ("n_unit_cm3", ctypes.c_double),
+        ("T_unit_K", ctypes.c_double),
+        ("t_unit_s", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class MhdError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, strerror(status), status))
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def exported_names():
+    """Function names declared in include/mhdchem.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"\b(mhd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmhdchem.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_1608_08748_amd.build); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(MhdParams)
+    B = ctypes.c_void_p
+    sig = {
+        "mhd_workspace_bytes": ([P], ctypes.c_size_t),
+        "mhd_create": ([P, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "mhd_init_state": ([B, _D], ctypes.c_int),
+        "mhd_set_state": ([B, _D], ctypes.c_int),
+        "mhd_get_state": ([B, _D], ctypes.c_int),
+        "mhd_cfl_dt": ([B, _D], ctypes.c_int),
+        "mhd_step": ([B, ctypes.c_double], ctypes.c_int),
+        "mhd_step_cfl": ([B], ctypes.c_int),
+        "mhd_conserved_totals": ([B, _D], ctypes.c_int),
+        "mhd_debug_stage": ([B, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+        "mhd_destroy": ([B], ctypes.c_int),
+        "mhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def strerror(status):
+    return lib().mhd_strerror(int(status)).decode()
+
+
+def _check(status, what):
+    if status != MHD_OK:
+        raise MhdError(status, what)
+
+
+def make_params(shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None):
+    nz, ny, nx = shape
+    p = MhdParams()
+    p.n[0], p.n[1], p.n[2] = nx, ny, nz
+    p.gamma, p.cfl, p.precision, p.theta = gamma, cfl, precision, theta
+    p.chemistry = 1 if chemistry else 0
+    p.n_unit_cm3, p.T_unit_K, p.t_unit_s = units if units is not None else DEFAULT_UNITS
+    return p
+
+
+def workspace_bytes(params):
+    return lib().mhd_workspace_bytes(ctypes.byref(params))
+
+
+class Box:
+    """One periodic box on one GPU.  shape = (nz, ny, nx)."""
+
+    def __init__(self, shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True,
+                 units=None, device="cuda", stream=None, workspace=None):
+        import torch
+        self.shape = tuple(int(s) for s in shape)
+        self.p = make_params(self.shape, precision, gamma, cfl, theta, chemistry, units)
+        nbytes = workspace_bytes(self.p)
+        if nbytes == 0:
+            raise MhdError(MHD_EINVAL, "mhd_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.ws = workspace
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        self.p.stream = self.stream.cuda_stream
+        self.p.workspace = self.ws.data_ptr()
+        self.p.workspace_bytes = self.ws.numel() * self.ws.element_size()
+        h = ctypes.c_void_p()
+        _check(lib().mhd_create(ctypes.byref(self.p), ctypes.byref(h)), "mhd_create")
+        self.h = h
+
+    @property
+    def ncell(self):
+        return self.shape[0] * self.shape[1] * self.shape[2]
+
+    def init_state(self, W):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        assert W.shape == (9,) + self.shape
+        _check(lib().mhd_init_state(self.h, W.ctypes.data_as(_D)), "mhd_init_state")
+
+    def set_state(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (10,) + self.shape
+        _check(lib().mhd_set_state(self.h, U.ctypes.data_as(_D)), "mhd_set_state")
+
+    def get_state(self):
+        U = np.empty((10,) + self.shape, dtype=np.float64)
+        _check(lib().mhd_get_state(self.h, U.ctypes.data_as(_D)), "mhd_get_state")
+        return U
+
+    def cfl_dt(self):
+        dt = ctypes.c_double()
+        _check(lib().mhd_cfl_dt(self.h, ctypes.byref(dt)), "mhd_cfl_dt")
+        return dt.value
+
+    def step(self, dt):
+        _check(lib().mhd_step(self.h, float(dt)), "mhd_step")
+
+    def step_cfl(self):
+        _check(lib().mhd_step_cfl(self.h), "mhd_step_cfl")
+
+    def totals(self):
+        out = np.zeros(10, dtype=np.float64)
+        _check(lib().mhd_conserved_totals(self.h, out.ctypes.data_as(_D)), "mhd_conserved_totals")
+        return out
+
+    def debug_stage(self, stage, dt):
+        _check(lib().mhd_debug_stage(self.h, int(stage), float(dt)), "mhd_debug_stage")
+
+    def run(self, steps):
+        """steps x {dt = cfl_dt(); step(dt)}; returns the dt list."""
+        dts = []
+        for _ in range(steps):
+            dt = self.cfl_dt()
+            self.step(dt)
+            dts.append(dt)
+        return dts
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mhd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

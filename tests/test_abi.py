@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every entry point include/mhdchem.h
+declares; host-only calls validate arguments.  No device work."""
+import ctypes
+
+import pytest
+
+from paper_1608_08748_amd import binding
+
+
+def test_every_declared_symbol_is_exported():
+    L = binding.lib()
+    names = binding.exported_names()
+    assert "mhd_step" in names and "mhd_cfl_dt" in names and "mhd_conserved_totals" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_bytes_scales_with_cells_and_precision():
+    p64 = binding.make_params((8, 8, 8), precision=binding.FP64)
+    p32 = binding.make_params((8, 8, 8), precision=binding.FP32_MIXED)
+    big = binding.make_params((16, 16, 16), precision=binding.FP64)
+    w64, w32, wb = (binding.workspace_bytes(p) for p in (p64, p32, big))
+    assert w64 > w32 > 0
+    assert 7 * w64 < wb < 9 * w64
+    # three state copies of 10 fields are the floor
+    assert w64 >= 3 * 10 * 512 * 8
+
+
+@pytest.mark.parametrize("field,value", [("gamma", 1.0), ("cfl", 0.0), ("theta", -1.0), ("precision", 7),
+                                         ("chemistry", 2)])
+def test_invalid_parameters_rejected(field, value):
+    p = binding.make_params((4, 4, 4))
+    setattr(p, field, value)
+    assert binding.workspace_bytes(p) == 0
+    h = ctypes.c_void_p()
+    assert binding.lib().mhd_create(ctypes.byref(p), ctypes.byref(h)) == binding.MHD_EINVAL
+
+
+def test_bad_dims_rejected():
+    p = binding.make_params((4, 4, 4))
+    p.n[1] = 0
+    assert binding.workspace_bytes(p) == 0
+    p = binding.make_params((2048, 2048, 2048))
+    assert binding.workspace_bytes(p) == 0
+
+
+def test_missing_or_small_workspace():
+    p = binding.make_params((4, 4, 4))
+    h = ctypes.c_void_p()
+    assert binding.lib().mhd_create(ctypes.byref(p), ctypes.byref(h)) == binding.MHD_ENOMEM
+    buf = ctypes.create_string_buffer(1 << 20)
+    p.workspace = ctypes.addressof(buf)
+    p.workspace_bytes = 16
+    assert binding.lib().mhd_create(ctypes.byref(p), ctypes.byref(h)) == binding.MHD_ENOMEM
+
+
+def test_null_box_and_bad_dt_rejected():
+    L = binding.lib()
+    assert L.mhd_step(None, 1e-3) == binding.MHD_EINVAL
+    assert L.mhd_cfl_dt(None, None) == binding.MHD_EINVAL
+
+
+def test_strerror():
+    for s in (0, -1, -2, -3, -4, -5):
+        assert binding.strerror(s)
+    assert binding.strerror(-99) == "unknown status"
