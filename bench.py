@@ -1,0 +1,172 @@
+"""Benchmark of the operator-split MHD + H2 chemistry step on one MI355X.
+
+    python bench.py [--config c2] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one full pass of the method over the box: NONADV stage (3 RK
+substages: primitive pass, face Riemann solves along x, y, z, flux / edge-field
+update), ADV stage (3 RK substages: face fluxes along x, y, z, update), tail
+(H2 clamp, FP64 chemistry, FP64 regularisation, CFL speed) and the CFL
+reduction.  The timed region is K x {dt = cfl_dt(); step(dt)} with the state
+resident in HBM, bracketed by device synchronisation.
+
+Workloads (synthetic, seeded; see paper_1608_08748_amd/inputs.py):
+  c2  256^3 FP64, rms Mach 5, beta 1, x_H2 1e-3, seed 2   (default)
+  c3  512^3 FP32 state (FP64 chemistry / reductions), rms Mach 5, beta 0.3,
+      seed 3, with the FP64 run of the same seed and dt sequence for the error
+  c1  32^3 FP64 white-noise box (the oracle's own configuration)
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s FP64 vs FP32 @≤1e-5 rel err; p50/p99 batched-solve latency"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic HBM bytes per cell for one launch of each kernel class, in
+# stored values (x 8 B for FP64, x 4 B for FP32): the fields the kernel must
+# read once and write once, with neighbour re-reads excluded
+ALG_VALUES = {
+    "prim": 8 + 8,            # rho, m(3), e, b(3) -> rho, v(3), Bc(3), p
+    "nonadv_face": 8 + 7,     # 7 primitives + face B_n -> 7 face outputs
+    "nonadv_update": 21 + 8 + 8 + 8,   # 3 x 7 face outputs, U and Q0 (8 fields each) -> 8 fields
+    "adv_face": 7 + 7,        # 7 advected fields -> 7 fluxes
+    "adv_update": 21 + 7 + 7 + 7,      # 3 x 7 fluxes, U, Q0 -> 7 fields
+    "tail": 10 + 2,           # state -> h2, e
+}
+
+
+def _config(name):
+    from paper_1608_08748_amd import binding, inputs
+    if name == "c1":
+        return dict(desc="c1: 32^3 periodic box, white-noise velocity sigma 0.1, B=(0.1,0,0), FP64",
+                    n=32, gen=lambda: inputs.c1(), precision=binding.FP64, steps=10, dtype="f64")
+    if name == "c2":
+        return dict(desc="c2: 256^3 periodic supersonic MHD turbulence, rms Mach 5, beta 1, x_H2 1e-3, FP64",
+                    n=256, gen=lambda: inputs.c2(), precision=binding.FP64, steps=100, dtype="f64")
+    if name == "c3":
+        return dict(desc="c3: 512^3 periodic MHD turbulence, rms Mach 5, beta 0.3, FP32 state/fluxes, "
+                         "FP64 chemistry/regularisation/CFL/totals",
+                    n=512, gen=lambda: inputs.c3(), precision=binding.FP32_MIXED, steps=200, dtype="f32+f64")
+    raise SystemExit("unknown config " + name)
+
+
+def _timed_run(box, steps, dts=None):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    used = []
+    for s in range(steps):
+        dt = box.cfl_dt() if dts is None else dts[s]
+        box.step(dt)
+        used.append(dt)
+    box.cfl_dt()            # waits for the last step
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, used
+
+
+def _roofline(timing, ncell, esz):
+    name, (ms, cnt) = max(((k, v) for k, v in timing.items() if k in ALG_VALUES), key=lambda kv: kv[1][0])
+    avg_s = ms / cnt / 1e3
+    alg_bytes = ALG_VALUES[name] * esz * ncell
+    gbs = alg_bytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(ms / cnt, 4), "launches": cnt,
+            "alg_bytes_per_launch": alg_bytes}
+
+
+def _cpu_baseline(n=96, steps=2):
+    import oracle
+    from paper_1608_08748_amd import inputs
+    oracle.build(force=False)
+    W = inputs.c2(n=n)
+    P = oracle.make_params(W.shape[1:])
+    U = oracle.prim_to_cons(P, W)
+    t0 = time.perf_counter()
+    oracle.run(P, U, steps)
+    el = time.perf_counter() - t0
+    return {"value": round(n ** 3 * steps / el, 1), "unit": "cell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": "c2 recipe (rms Mach 5, beta 1, seed 2) at %d^3, %d steps, %.1f s"
+            % (n, steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this implementation runs one box on one GPU; --gpus %d is not supported "
+              "(multi-GPU sharding is a design note only)" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1608_08748_amd import binding
+
+    cfg = _config(args.config)
+    steps = args.steps if args.steps is not None else cfg["steps"]
+    W = cfg["gen"]()
+    shape = W.shape[1:]
+    ncell = int(np.prod(shape))
+    torch.cuda.set_device(0)
+    box = binding.Box(shape, precision=cfg["precision"])
+    box.init_state(W)
+    for _ in range(args.warmup):
+        box.step(box.cfl_dt())
+    box.init_state(W)      # timed run starts from the initial condition
+
+    box.set_timing(True)
+    el, dts = _timed_run(box, steps)
+    timing = box.get_timing()
+    box.set_timing(False)
+    esz = 8 if cfg["precision"] == binding.FP64 else 4
+    out = {
+        "metric": METRIC, "value": round(ncell * steps / el, 1), "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(el / steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": cfg["dtype"],
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "cells": ncell, "grid": list(shape)[::-1], "cfl": 0.3,
+                   "gamma": 5.0 / 3.0, "theta": 1.0, "parallelism": "single GPU"},
+        "roofline": _roofline(timing, ncell, esz),
+        "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
+    }
+    tot = box.totals()
+    out["totals_end"] = [float(x) for x in tot]
+    if args.config == "c3":
+        # the FP64 run of the same seed with the same dt sequence, for the error
+        del box
+        torch.cuda.empty_cache()
+        ref = binding.Box(shape, precision=binding.FP64)
+        ref.init_state(W)
+        el64, _ = _timed_run(ref, steps, dts)
+        t64 = ref.totals()
+        G64 = None
+        absq = None
+        try:
+            G64 = ref.get_state()
+            absq = np.abs(G64).reshape(10, -1).sum(axis=1)
+        except MemoryError:
+            pass
+        if absq is not None:
+            out["fp32_total_rel_err"] = {binding.FIELDS[f]: float(abs(tot[f] - t64[f]) / absq[f])
+                                         for f in range(10)}
+        out["fp64_same_seed"] = {"value": round(ncell * steps / el64, 1), "ms_per_step": round(el64 / steps * 1e3, 3)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

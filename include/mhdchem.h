@@ -140,6 +140,28 @@ int mhd_conserved_totals(mhd_box *b, double out[10]);
  * for per-stage parity checks.  Asynchronous. */
 int mhd_debug_stage(mhd_box *b, int stage, double dt);
 
+/* Kernel classes timed by mhd_set_timing / mhd_get_timing. */
+enum {
+    MHD_K_PRIM = 0,          /* NONADV primitive pass                 */
+    MHD_K_NONADV_FACE = 1,   /* NONADV face Riemann solve (per axis)  */
+    MHD_K_NONADV_UPDATE = 2, /* NONADV flux/CT update + RK            */
+    MHD_K_ADV_FACE = 3,      /* ADV face fluxes (per axis)            */
+    MHD_K_ADV_UPDATE = 4,    /* ADV update + RK                       */
+    MHD_K_TAIL = 5,          /* clamp, chemistry, regularisation, CFL */
+    MHD_K_REDUCE = 6,        /* CFL / totals reductions               */
+    MHD_NKCLASS = 7
+};
+
+/* Enable (1) or disable (0) per-launch HIP-event timing of the step's
+ * kernels on the box's stream; enabling clears the accumulators.  While
+ * enabled, each mhd_step / mhd_step_cfl waits for its own last kernel
+ * (so the step becomes synchronous). */
+int mhd_set_timing(mhd_box *b, int enable);
+
+/* Accumulated device time (ms) and launch count per kernel class since
+ * timing was enabled.  ms and counts have MHD_NKCLASS entries. */
+int mhd_get_timing(mhd_box *b, double *ms, int64_t *counts);
+
 /* Release the box (not the workspace, not the stream). */
 int mhd_destroy(mhd_box *b);
 

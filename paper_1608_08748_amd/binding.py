@@ -18,6 +18,8 @@ MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ECFL, MHD_ENONPHYS = 0, -1, -2,
 FP64, FP32_MIXED = 0, 1
 STAGE_NONADV, STAGE_ADV, STAGE_TAIL, STAGE_NONADV_RHS, STAGE_ADV_RHS = 1, 2, 3, 4, 5
 FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2")
+KCLASSES = ("prim", "nonadv_face", "nonadv_update", "adv_face", "adv_update", "tail", "reduce")
+NKCLASS = len(KCLASSES)
 
 # chemistry unit map: 5 H nuclei per cm^3 per unit density, T_u = 5000 K,
 # t_u = L_u / v_u with L_u = 256 pc and v_u = sqrt(k_B T_u / m_H)
@@ -82,6 +84,8 @@ def lib():
         "mhd_debug_stage": ([B, ctypes.c_int, ctypes.c_double], ctypes.c_int),
         "mhd_destroy": ([B], ctypes.c_int),
         "mhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "mhd_set_timing": ([B, ctypes.c_int], ctypes.c_int),
+        "mhd_get_timing": ([B, _D, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -173,6 +177,17 @@ class Box:
 
     def debug_stage(self, stage, dt):
         _check(lib().mhd_debug_stage(self.h, int(stage), float(dt)), "mhd_debug_stage")
+
+    def set_timing(self, enable):
+        _check(lib().mhd_set_timing(self.h, 1 if enable else 0), "mhd_set_timing")
+
+    def get_timing(self):
+        """{class name: (ms total, launches)} since timing was enabled."""
+        ms = np.zeros(NKCLASS, dtype=np.float64)
+        cnt = np.zeros(NKCLASS, dtype=np.int64)
+        _check(lib().mhd_get_timing(self.h, ms.ctypes.data_as(_D),
+                                    cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "mhd_get_timing")
+        return {KCLASSES[i]: (float(ms[i]), int(cnt[i])) for i in range(NKCLASS)}
 
     def run(self, steps):
         """steps x {dt = cfl_dt(); step(dt)}; returns the dt list."""

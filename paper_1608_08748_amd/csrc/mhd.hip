@@ -737,6 +737,14 @@ struct mhd_box {
     double* dt_dev;
     double* tot_dev;
     int cur[3];        // current slot of the groups H, M, B
+    // per-launch event timing (mhd_set_timing)
+    int timing;
+    int nev;                    // event pairs recorded in the current step
+    hipEvent_t ev[2 * 64];
+    int evcls[64];
+    int ev_ready;
+    double tms[MHD_NKCLASS];
+    int64_t tcnt[MHD_NKCLASS];
 };
 
 namespace {
@@ -837,6 +845,38 @@ const RK rk_coef[3] = { { 0.0, 1.0 }, { 0.75, 0.25 }, { 1.0 / 3.0, 2.0 / 3.0 } }
 
 struct Slots { int h, m, b; };
 
+// event pair around one launch of class cls (no-op unless timing is on)
+struct KTimer {
+    mhd_box* b;
+    int slot;
+    KTimer(mhd_box* box, int cls) : b(box), slot(-1)
+    {
+        if (b->timing && b->nev < 64) {
+            slot = b->nev++;
+            b->evcls[slot] = cls;
+            hipEventRecord(b->ev[2 * slot], b->s);
+        }
+    }
+    ~KTimer()
+    {
+        if (slot >= 0) hipEventRecord(b->ev[2 * slot + 1], b->s);
+    }
+};
+
+int timing_collect(mhd_box* b)
+{
+    if (!b->timing || b->nev == 0) return MHD_OK;
+    if (hipEventSynchronize(b->ev[2 * (b->nev - 1) + 1]) != hipSuccess) return MHD_EDEVICE;
+    for (int i = 0; i < b->nev; i++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->ev[2 * i], b->ev[2 * i + 1]) != hipSuccess) return MHD_EDEVICE;
+        b->tms[b->evcls[i]] += ms;
+        b->tcnt[b->evcls[i]] += 1;
+    }
+    b->nev = 0;
+    return MHD_OK;
+}
+
 template <typename T>
 int nonadv_substage(mhd_box* b, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg, bool first)
 {
@@ -848,11 +888,26 @@ int nonadv_substage(mhd_box* b, Slots sin, Slots sS, Slots sout, const StepArgs&
     T* F0 = reinterpret_cast<T*>(b->F[0]);
     T* F1 = reinterpret_cast<T*>(b->F[1]);
     T* F2 = reinterpret_cast<T*>(b->F[2]);
-    k_prim<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), W, a, b->flags, first ? b->dt_dev : nullptr);
-    k_nonadv_face<T, 0><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BX], F0, a);
-    k_nonadv_face<T, 1><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BY], F1, a);
-    k_nonadv_face<T, 2><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BZ], F2, a);
-    k_nonadv_update<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), cview(S), out, F0, F1, F2, a, rk, dbg);
+    {
+        KTimer t(b, MHD_K_PRIM);
+        k_prim<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), W, a, b->flags, first ? b->dt_dev : nullptr);
+    }
+    {
+        KTimer t(b, MHD_K_NONADV_FACE);
+        k_nonadv_face<T, 0><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BX], F0, a);
+    }
+    {
+        KTimer t(b, MHD_K_NONADV_FACE);
+        k_nonadv_face<T, 1><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BY], F1, a);
+    }
+    {
+        KTimer t(b, MHD_K_NONADV_FACE);
+        k_nonadv_face<T, 2><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BZ], F2, a);
+    }
+    {
+        KTimer t(b, MHD_K_NONADV_UPDATE);
+        k_nonadv_update<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), cview(S), out, F0, F1, F2, a, rk, dbg);
+    }
     return launch_status();
 }
 
@@ -866,10 +921,22 @@ int adv_substage(mhd_box* b, Slots sin, Slots sS, Slots sout, const StepArgs& a,
     T* F0 = reinterpret_cast<T*>(b->F[0]);
     T* F1 = reinterpret_cast<T*>(b->F[1]);
     T* F2 = reinterpret_cast<T*>(b->F[2]);
-    k_adv_face<T, 0><<<grid, blk, 0, b->s>>>(b->g, cview(in), F0, a);
-    k_adv_face<T, 1><<<grid, blk, 0, b->s>>>(b->g, cview(in), F1, a);
-    k_adv_face<T, 2><<<grid, blk, 0, b->s>>>(b->g, cview(in), F2, a);
-    k_adv_update<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), cview(S), out, F0, F1, F2, a, rk, dbg);
+    {
+        KTimer t(b, MHD_K_ADV_FACE);
+        k_adv_face<T, 0><<<grid, blk, 0, b->s>>>(b->g, cview(in), F0, a);
+    }
+    {
+        KTimer t(b, MHD_K_ADV_FACE);
+        k_adv_face<T, 1><<<grid, blk, 0, b->s>>>(b->g, cview(in), F1, a);
+    }
+    {
+        KTimer t(b, MHD_K_ADV_FACE);
+        k_adv_face<T, 2><<<grid, blk, 0, b->s>>>(b->g, cview(in), F2, a);
+    }
+    {
+        KTimer t(b, MHD_K_ADV_UPDATE);
+        k_adv_update<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), cview(S), out, F0, F1, F2, a, rk, dbg);
+    }
     return launch_status();
 }
 
@@ -912,9 +979,15 @@ template <typename T>
 int tail(mhd_box* b, const StepArgs& a, int mode)
 {
     Fields<T> u = view<T>(b, b->cur[GH], b->cur[GM], b->cur[GB]);
-    k_tail<T><<<b->nblocks, NTH, 0, b->s>>>(b->g, u, a, chem_args(b), mode, b->part, b->flags);
+    {
+        KTimer t(b, MHD_K_TAIL);
+        k_tail<T><<<b->nblocks, NTH, 0, b->s>>>(b->g, u, a, chem_args(b), mode, b->part, b->flags);
+    }
     double cflh = b->p.cfl * (1.0 / (double)b->p.n[0]);
-    k_reduce_dt<<<1, 1024, 0, b->s>>>(b->part, b->nblocks, cflh, b->dt_dev);
+    {
+        KTimer t(b, MHD_K_REDUCE);
+        k_reduce_dt<<<1, 1024, 0, b->s>>>(b->part, b->nblocks, cflh, b->dt_dev);
+    }
     return launch_status();
 }
 
@@ -925,7 +998,8 @@ int full_step(mhd_box* b, double dt, bool dev)
     int st;
     if ((st = nonadv_stage<T>(b, a, true))) return st;
     if ((st = adv_stage<T>(b, a))) return st;
-    return tail<T>(b, a, 1);
+    if ((st = tail<T>(b, a, 1))) return st;
+    return timing_collect(b);
 }
 
 int sync_and_flags(mhd_box* b)
@@ -1059,7 +1133,43 @@ int mhd_create(const mhd_params* p, mhd_box** out)
     b->dt_dev = reinterpret_cast<double*>(w + 256);
     b->tot_dev = reinterpret_cast<double*>(w + 512);
     b->cur[0] = b->cur[1] = b->cur[2] = 0;
+    b->timing = 0;
+    b->nev = 0;
+    b->ev_ready = 0;
+    for (int c = 0; c < MHD_NKCLASS; c++) {
+        b->tms[c] = 0.0;
+        b->tcnt[c] = 0;
+    }
     *out = b;
+    return MHD_OK;
+}
+
+int mhd_set_timing(mhd_box* b, int enable)
+{
+    if (!b) return MHD_EINVAL;
+    if (enable && !b->ev_ready) {
+        for (int i = 0; i < 2 * 64; i++)
+            if (hipEventCreate(&b->ev[i]) != hipSuccess) return MHD_EDEVICE;
+        b->ev_ready = 1;
+    }
+    b->timing = enable ? 1 : 0;
+    b->nev = 0;
+    for (int c = 0; c < MHD_NKCLASS; c++) {
+        b->tms[c] = 0.0;
+        b->tcnt[c] = 0;
+    }
+    return MHD_OK;
+}
+
+int mhd_get_timing(mhd_box* b, double* ms, int64_t* counts)
+{
+    if (!b || !ms || !counts) return MHD_EINVAL;
+    int st = timing_collect(b);
+    if (st) return st;
+    for (int c = 0; c < MHD_NKCLASS; c++) {
+        ms[c] = b->tms[c];
+        counts[c] = b->tcnt[c];
+    }
     return MHD_OK;
 }
 
@@ -1117,6 +1227,8 @@ int mhd_debug_stage(mhd_box* b, int stage, double dt)
 
 int mhd_destroy(mhd_box* b)
 {
+    if (b && b->ev_ready)
+        for (int i = 0; i < 2 * 64; i++) hipEventDestroy(b->ev[i]);
     delete b;
     return MHD_OK;
 }
