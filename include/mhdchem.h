@@ -124,7 +124,9 @@ int mhd_cfl_dt(mhd_box *b, double *dt_out);
 /* Advance the state by dt: NONADV, ADV, H2 clamp to [0, rho], chemistry,
  * regularisation; then the CFL step of the new state is computed on the
  * device.  Asynchronous.  dt must be finite and > 0 (else MHD_EINVAL); a dt
- * above the CFL bound of the start state latches MHD_ECFL. */
+ * above the CFL bound of the start state (relative slack 1e-12 for MHD_FP64,
+ * 1e-4 for MHD_FP32_MIXED, whose bound comes from FP32 values) latches
+ * MHD_ECFL. */
 int mhd_step(mhd_box *b, double dt);
 
 /* As mhd_step with the device-resident CFL step of the current state
