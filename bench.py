@@ -82,7 +82,7 @@ def _roofline(timing, ncell, esz):
             "alg_bytes_per_launch": alg_bytes}
 
 
-def _cpu_baseline(n=96, steps=2):
+def _cpu_baseline(n=192, steps=3):
     import oracle
     from paper_1608_08748_amd import inputs
     oracle.build(force=False)
