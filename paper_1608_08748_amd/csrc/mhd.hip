@@ -76,30 +76,35 @@ template <typename T> struct CFields { const T* f[NF]; };
 
 template <typename T> struct Par { T qL, qR, dq, q6; };
 
-// Step 1: limited central difference
+// Step 1: limited central difference (min of the three candidates, sign of
+// the central difference; zero at extrema)
 template <typename T>
 __device__ __forceinline__ T limited_slope(T qm, T q0, T qp)
 {
     T dq = T(0.5) * (qp - qm);
-    T m = fabs(dq);
     T a = T(2) * fabs(qp - q0);
     T b = T(2) * fabs(q0 - qm);
-    m = a < m ? a : m;
-    m = b < m ? b : m;
-    T r = dq >= T(0) ? m : -m;
-    return ((qp - q0) * (q0 - qm) > T(0)) ? r : T(0);
+    T m = fmin(fmin(fabs(dq), a), b);
+    return ((qp - q0) * (q0 - qm) > T(0)) ? copysign(m, dq) : T(0);
 }
 
-// Steps 1-5 for the cell with line values qmm, qm, q0, qp, qpp
+// Step 1: fourth-order interface value q_{j+1/2} = 1/2 (q_j + q_{j+1}) - 1/6 (dm_{j+1} - dm_j)
 template <typename T>
-__device__ __forceinline__ Par<T> parabola(T qmm, T qm, T q0, T qp, T qpp)
+__device__ __forceinline__ T interface_value(T q0, T q1, T dm0, T dm1)
 {
-    const T sixth = T(1.0 / 6.0);
-    T dm_m = limited_slope(qmm, qm, q0);
-    T dm_0 = limited_slope(qm, q0, qp);
-    T dm_p = limited_slope(q0, qp, qpp);
-    T qL = T(0.5) * (qm + q0) - sixth * (dm_0 - dm_m);
-    T qR = T(0.5) * (q0 + qp) - sixth * (dm_p - dm_0);
+    return T(0.5) * (q0 + q1) - T(1.0 / 6.0) * (dm1 - dm0);
+}
+
+// margins that decide a saturated Step-4 weight without the division
+template <typename T> struct EtaMargin;
+template <> struct EtaMargin<double> { static constexpr double lo = 0.05 * (1.0 - 1e-9), hi = 0.1 * (1.0 + 1e-9); };
+template <> struct EtaMargin<float> { static constexpr float lo = 0.05f * (1.0f - 1e-5f), hi = 0.1f * (1.0f + 1e-5f); };
+
+// Steps 2-5 for cell j with line values qmm..qpp, Step-1 edge values qL, qR
+// and limited slope dm of the cell
+template <typename T>
+__device__ __forceinline__ Par<T> parabola_finish(T qmm, T qm, T q0, T qp, T qpp, T qL, T qR, T dm)
+{
     // Step 2: monotone edge values
     T dq = qR - qL;
     T q6 = T(6) * (q0 - T(0.5) * (qL + qR));
@@ -108,31 +113,67 @@ __device__ __forceinline__ Par<T> parabola(T qmm, T qm, T q0, T qp, T qpp)
     bool overR = dq * q6 < -(dq * dq);
     T nL = flat ? q0 : (overL ? T(3) * q0 - T(2) * qR : qL);
     T nR = flat ? q0 : ((!overL && overR) ? T(3) * q0 - T(2) * qL : qR);
-    qL = nL;
-    qR = nR;
-    // Step 4: discontinuity detector (second differences; h^2 cancels)
-    T qLp = q0 - T(0.25) * dm_0;
-    T qRp = q0 + T(0.25) * dm_0;
+    // Step 4: discontinuity detector on second differences (h^2 cancels)
+    T qLp = q0 - T(0.25) * dm;
+    T qRp = q0 + T(0.25) * dm;
     T Dm = q0 - T(2) * qm + qmm;
     T Dp = qpp - T(2) * qp + q0;
     T aqp = fabs(qp), aqm = fabs(qm);
-    T mn = aqm < aqp ? aqm : aqp;
-    T sa = aqp + aqm;
-    mn = sa < mn ? sa : mn;
+    T mn = fmin(fmin(aqp, aqm), aqp + aqm);
     bool zero_eta = (fabs(qp - qm) - T(0.01) * mn <= T(0)) || (Dp * Dm > T(0));
-    T den = zero_eta ? T(1) : T(6) * (qp - qm);
-    T eta = zero_eta ? T(0) : -(Dp - Dm) / den;
-    T w = T(20) * (eta - T(0.05));
-    w = w > T(1) ? T(1) : w;
-    w = w < T(0) ? T(0) : w;
-    qL = (T(1) - w) * qL + w * qLp;
-    qR = (T(1) - w) * qR + w * qRp;
+    // eta = t / d; the weight w = clamp(20 (eta - 0.05), 0, 1) is exactly 0
+    // or 1 outside a band around [0.05, 0.1], decided by products with a
+    // relative margin far above rounding; the division runs only inside it
+    T t = -(Dp - Dm);
+    T d = T(6) * (qp - qm);
+    T ts = d < T(0) ? -t : t;
+    T ds = fabs(d);
+    bool sat_hi = !zero_eta && ts >= EtaMargin<T>::hi * ds;
+    bool need = !zero_eta && !sat_hi && !(ts <= EtaMargin<T>::lo * ds);
+    T w = sat_hi ? T(1) : T(0);
+    if (need) {
+        T eta = t / d;
+        w = fmin(fmax(T(20) * (eta - T(0.05)), T(0)), T(1));
+    }
+    T fL = (T(1) - w) * nL + w * qLp;
+    T fR = (T(1) - w) * nR + w * qRp;
+    // Step 5
     Par<T> p;
-    p.qL = qL;
-    p.qR = qR;
-    p.dq = qR - qL;
-    p.q6 = T(6) * (q0 - T(0.5) * (qL + qR));
+    p.qL = fL;
+    p.qR = fR;
+    p.dq = fR - fL;
+    p.q6 = T(6) * (q0 - T(0.5) * (fL + fR));
     return p;
+}
+
+// Steps 1-5 for the cell with line values qmm, qm, q0, qp, qpp
+template <typename T>
+__device__ __forceinline__ Par<T> parabola(T qmm, T qm, T q0, T qp, T qpp)
+{
+    T dm_m = limited_slope(qmm, qm, q0);
+    T dm_0 = limited_slope(qm, q0, qp);
+    T dm_p = limited_slope(q0, qp, qpp);
+    T qL = interface_value(qm, q0, dm_m, dm_0);
+    T qR = interface_value(q0, qp, dm_0, dm_p);
+    return parabola_finish(qmm, qm, q0, qp, qpp, qL, qR, dm_0);
+}
+
+// parabolas of the two cells on either side of a face from the 6-cell line
+// q0..q5 (cells i-3..i+2; left cell i-1, right cell i): the middle slopes and
+// the face value q_{i-1/2} are shared, so this is the same arithmetic as two
+// separate calls
+template <typename T>
+__device__ __forceinline__ void parabola_pair(T q0, T q1, T q2, T q3, T q4, T q5, Par<T>& PL, Par<T>& PR)
+{
+    T d1 = limited_slope(q0, q1, q2);
+    T d2 = limited_slope(q1, q2, q3);
+    T d3 = limited_slope(q2, q3, q4);
+    T d4 = limited_slope(q3, q4, q5);
+    T f12 = interface_value(q1, q2, d1, d2);
+    T f23 = interface_value(q2, q3, d2, d3);
+    T f34 = interface_value(q3, q4, d3, d4);
+    PL = parabola_finish(q0, q1, q2, q3, q4, f12, f23, d2);
+    PR = parabola_finish(q1, q2, q3, q4, q5, f23, f34, d3);
 }
 
 // Sec. 2.4: average over the right part of relative width y (the q(-nu t) formula)
@@ -193,102 +234,103 @@ __global__ __launch_bounds__(NTH) void k_prim(Geo g, CFields<T> U, T* __restrict
     W[7 * N + c] = T(a.gamma - 1.0) * U.f[EI][c];
 }
 
-// NONADV face state (Sec. 2.4) at the lower face of every cell along D, and
-// the fluxes and edge-field contributions it produces.  Outputs, 7 x N:
-//   0..2 momentum flux (normal, t1, t2), 3 energy flux, 4 face normal velocity,
-//   5 E along t1 (B_t2 U_n - B_n U_t2), 6 E along t2 (B_n U_t1 - B_t1 U_n)
-template <typename T, int D>
-__global__ __launch_bounds__(NTH) void k_nonadv_face(Geo g, const T* __restrict__ W, const T* __restrict__ bface,
-                                                     T* __restrict__ F, StepArgs a)
+// What one side of a face needs from a cell's parabolas (6 variables): the
+// edge value facing the face (qR of the left cell, qL of the right cell), dq
+// and q6.
+template <typename T> struct Side { T e[6], dq[6], q6[6]; };
+
+template <typename T>
+__device__ __forceinline__ void side_left(const Par<T>& P, Side<T>& S, int v)
 {
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-    int i, j, k;
-    decompose(g, c, i, j, k);
-    const size_t N = (size_t)g.n;
-    int idx[6];
-#pragma unroll
-    for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
+    S.e[v] = P.qR;
+    S.dq[v] = P.dq;
+    S.q6[v] = P.q6;
+}
 
-    const T gm = T(a.gamma);
-    const T ydx = T(a.theta * (step_dt(a) / a.h));
+template <typename T>
+__device__ __forceinline__ void side_right(const Par<T>& P, Side<T>& S, int v)
+{
+    S.e[v] = P.qL;
+    S.dq[v] = P.dq;
+    S.q6[v] = P.q6;
+}
+
+// NONADV face state (Sec. 2.4) of one face and the fluxes and edge-field
+// contributions it produces.  Inputs: cell-centre rho, p, Bt1, Bt2 of the left
+// and right cells, the face normal field bn, the two sides' parabolas of
+// (vn, vt1, vt2, Bt1, Bt2, p).  Outputs (7): momentum flux (normal, t1, t2),
+// energy flux, face normal velocity, E along t1 (B_t2 U_n - B_n U_t2), E along
+// t2 (B_n U_t1 - B_t1 U_n).
+template <typename T>
+__device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr, T b1r, T b2r, T bn,
+                                           const Side<T>& L, const Side<T>& R, T gm, T ydx, T out[7])
+{
     const T eps = Eps<T>::v;
-
-    // face averages from the two cell centres (sqrt(rho) weights; cross weights for Bt)
-    T rl = W[idx[2]], rr = W[idx[3]];
-    T pl = W[7 * N + idx[2]], pr = W[7 * N + idx[3]];
-    T b1l = W[(4 + T1) * N + idx[2]], b1r = W[(4 + T1) * N + idx[3]];
-    T b2l = W[(4 + T2) * N + idx[2]], b2r = W[(4 + T2) * N + idx[3]];
+    // face averages (sqrt(rho) weights; cross weights for Bt)
     T sl = sqrt(rl), sr = sqrt(rr);
-    T wsum = sl + sr;
-    T rho = (sl * rl + sr * rr) / wsum;
-    T p = (sl * pl + sr * pr) / wsum;
-    T bt1 = (sl * b1r + sr * b1l) / wsum;
-    T bt2 = (sl * b2r + sr * b2l) / wsum;
-    T bn = bface[c];
+    T iw = T(1) / (sl + sr);
+    T rho = (sl * rl + sr * rr) * iw;
+    T p = (sl * pl + sr * pr) * iw;
+    T bt1 = (sl * b1r + sr * b1l) * iw;
+    T bt2 = (sl * b2r + sr * b2l) * iw;
 
     // eigen-structure (Sec. 2.3, 2.4, eigenvector appendix)
-    T c2 = gm * p / rho;
-    T ca2 = bn * bn / rho;
-    T b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) / rho;
+    T irho = T(1) / rho;
+    T c2 = gm * p * irho;
+    T ca2 = bn * bn * irho;
+    T b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) * irho;
     T s = c2 + b2;
-    T disc = s * s - T(4) * c2 * ca2;
-    disc = disc < T(0) ? T(0) : disc;
+    T disc = fmax(s * s - T(4) * c2 * ca2, T(0));
     T sd = sqrt(disc);
     T cf2 = T(0.5) * (s + sd);
-    T cs2 = T(0.5) * (s - sd);
-    cs2 = cs2 < T(0) ? T(0) : cs2;
+    T cs2 = fmax(T(0.5) * (s - sd), T(0));
     T cc = sqrt(c2), ca = sqrt(ca2), cf = sqrt(cf2), cs = sqrt(cs2);
     const T r2i = T(0.70710678118654752440);
     T den = cf2 - cs2;
-    T af, as;
+    T af = r2i, as = r2i;
     if (den > eps * s) {
-        T nf = c2 - cs2, ns = cf2 - c2;
-        nf = nf < T(0) ? T(0) : nf;
-        ns = ns < T(0) ? T(0) : ns;
-        af = sqrt(nf / den);
-        as = sqrt(ns / den);
-    } else {
-        af = r2i;
-        as = r2i;
+        T iden = T(1) / den;
+        af = sqrt(fmax(c2 - cs2, T(0)) * iden);
+        as = sqrt(fmax(cf2 - c2, T(0)) * iden);
     }
-    T by, bz;
+    T by = r2i, bz = r2i;
     T btsq = bt1 * bt1 + bt2 * bt2;
     if (btsq > eps * (bn * bn + btsq + gm * p)) {
-        T bt = sqrt(btsq);
-        by = bt1 / bt;
-        bz = bt2 / bt;
-    } else {
-        by = r2i;
-        bz = r2i;
+        T ibt = T(1) / sqrt(btsq);
+        by = bt1 * ibt;
+        bz = bt2 * ibt;
     }
     T sg = bn >= T(0) ? T(1) : T(-1);
     T srho = sqrt(rho);
 
-    // parabola averages of the six variables on the upwind side of each wave
-    T yf = ydx * cf, ys = ydx * cs, ya = ydx * ca;
+    // parabola averages on the upwind side of each wave: waves +cf, +cs, +ca
+    // read the left cell (right part, q(-nu t)), waves -cf, -cs, -ca the right
+    // cell (left part, q(+nu t))
     T qf[6], qfm[6], qs[6], qsm[6], qa[6], qam[6];
-    constexpr int var_field[6] = { 1 + D, 1 + T1, 1 + T2, 4 + T1, 4 + T2, 7 };
+    T y3[3] = { ydx * cf, ydx * cs, ydx * ca };
+    T hy[3], ky[3];
+#pragma unroll
+    for (int w = 0; w < 3; w++) {
+        hy[w] = T(0.5) * y3[w];
+        ky[w] = T(1) - T(2.0 / 3.0) * y3[w];
+    }
 #pragma unroll
     for (int v = 0; v < 6; v++) {
-        const T* q = W + (size_t)var_field[v] * N;
-        T l0 = q[idx[0]], l1 = q[idx[1]], l2 = q[idx[2]], l3 = q[idx[3]], l4 = q[idx[4]], l5 = q[idx[5]];
-        Par<T> PL = parabola(l0, l1, l2, l3, l4);
-        Par<T> PR = parabola(l1, l2, l3, l4, l5);
-        qf[v] = avg_right(PL, yf);
-        qfm[v] = avg_left(PR, yf);
-        qs[v] = avg_right(PL, ys);
-        qsm[v] = avg_left(PR, ys);
-        qa[v] = avg_right(PL, ya);
-        qam[v] = avg_left(PR, ya);
+        qf[v] = L.e[v] - hy[0] * (L.dq[v] - L.q6[v] * ky[0]);
+        qs[v] = L.e[v] - hy[1] * (L.dq[v] - L.q6[v] * ky[1]);
+        qa[v] = L.e[v] - hy[2] * (L.dq[v] - L.q6[v] * ky[2]);
+        qfm[v] = R.e[v] + hy[0] * (R.dq[v] + R.q6[v] * ky[0]);
+        qsm[v] = R.e[v] + hy[1] * (R.dq[v] + R.q6[v] * ky[1]);
+        qam[v] = R.e[v] + hy[2] * (R.dq[v] + R.q6[v] * ky[2]);
     }
 
     // characteristic amplitudes s_k = l_k . q_up(k)
-    T A = T(1) / (T(2) * c2);            // 1 / (2 c^2)
-    T Bc = T(1) / (T(2) * srho * cc);    // 1 / (2 sqrt(rho) c)
-    T Cc = T(1) / (T(2) * rho * c2);     // 1 / (2 rho c^2)
-    T Dc = T(1) / sqrt(T(2) * rho);      // 1 / sqrt(2 rho)
+    T ic2 = T(1) / c2;
+    T isc = T(1) / (srho * cc);
+    T A = T(0.5) * ic2;                  // 1 / (2 c^2)
+    T Bc = T(0.5) * isc;                 // 1 / (2 sqrt(rho) c)
+    T Cc = A * irho;                     // 1 / (2 rho c^2)
+    T Dc = r2i / srho;                   // 1 / sqrt(2 rho)
     T afcf = af * cf, ascs = as * cs;
     auto vtb = [&](const T* q) { return by * q[1] + bz * q[2]; };
     auto btb = [&](const T* q) { return by * q[3] + bz * q[4]; };
@@ -304,7 +346,7 @@ __global__ __launch_bounds__(NTH) void k_nonadv_face(Geo g, const T* __restrict_
     // face state q = sum_k r_k s_k
     T fdm = s0 - s1, fsm = s0 + s1, sdm = s2 - s3, ssm = s2 + s3, adm = s4 - s5, asm_ = s4 + s5;
     T src = srho * cc;
-    T sr2 = sqrt(rho * T(0.5));
+    T sr2 = r2i * srho;
     T gp = gm * p;
     T Vn = afcf * fdm + ascs * sdm;
     T Vt1 = sg * by * (-ascs * fdm + afcf * sdm) - bz * sg * r2i * asm_;
@@ -316,13 +358,174 @@ __global__ __launch_bounds__(NTH) void k_nonadv_face(Geo g, const T* __restrict_
     // fluxes of the non-advective equations and edge-field contributions
     T Pst = P + T(0.5) * (bn * bn + Bt1 * Bt1 + Bt2 * Bt2);
     T BV = bn * Vn + Bt1 * Vt1 + Bt2 * Vt2;
-    F[0 * N + c] = Pst - bn * bn;
-    F[1 * N + c] = -(bn * Bt1);
-    F[2 * N + c] = -(bn * Bt2);
-    F[3 * N + c] = Pst * Vn - bn * BV;
-    F[4 * N + c] = Vn;
-    F[5 * N + c] = Bt2 * Vn - bn * Vt2;
-    F[6 * N + c] = bn * Vt1 - Bt1 * Vn;
+    out[0] = Pst - bn * bn;
+    out[1] = -(bn * Bt1);
+    out[2] = -(bn * Bt2);
+    out[3] = Pst * Vn - bn * BV;
+    out[4] = Vn;
+    out[5] = Bt2 * Vn - bn * Vt2;
+    out[6] = bn * Vt1 - Bt1 * Vn;
+}
+
+// primitive-array slots of the six parabola variables for faces along D:
+// (vn, vt1, vt2, Bt1, Bt2, p) in the W layout rho, vx, vy, vz, Bcx, Bcy, Bcz, p
+template <int D> struct Vars {
+    static constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    static constexpr int f[6] = { 1 + D, 1 + T1, 1 + T2, 4 + T1, 4 + T2, 7 };
+};
+
+template <typename T>
+__device__ __forceinline__ void store_face(T* __restrict__ F, size_t N, int c, const T out[7])
+{
+#pragma unroll
+    for (int q = 0; q < 7; q++) F[q * N + c] = out[q];
+}
+
+// NONADV faces along D, one face per thread, both adjacent parabolas computed
+// by the thread (general fallback for any box)
+template <typename T, int D>
+__global__ __launch_bounds__(NTH) void k_nonadv_face(Geo g, const T* __restrict__ W, const T* __restrict__ bface,
+                                                     T* __restrict__ F, StepArgs a)
+{
+    int c = blockIdx.x * NTH + threadIdx.x;
+    if (c >= g.n) return;
+    using V = Vars<D>;
+    int i, j, k;
+    decompose(g, c, i, j, k);
+    const size_t N = (size_t)g.n;
+    int idx[6];
+#pragma unroll
+    for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
+    Side<T> L, R;
+#pragma unroll
+    for (int v = 0; v < 6; v++) {
+        const T* q = W + (size_t)V::f[v] * N;
+        Par<T> PL, PR;
+        parabola_pair(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], PL, PR);
+        side_left(PL, L, v);
+        side_right(PR, R, v);
+    }
+    T out[7];
+    face_solve(W[idx[2]], W[7 * N + idx[2]], W[(size_t)V::f[3] * N + idx[2]], W[(size_t)V::f[4] * N + idx[2]],
+               W[idx[3]], W[7 * N + idx[3]], W[(size_t)V::f[3] * N + idx[3]], W[(size_t)V::f[4] * N + idx[3]],
+               bface[c], L, R, T(a.gamma), T(a.theta * (step_dt(a) / a.h)), out);
+    store_face(F, N, c, out);
+}
+
+// NONADV faces along x with whole x rows per block: each thread computes the
+// parabolas of its own cell once; the left neighbour's side comes from LDS
+// (periodic wrap inside the row), so no parabola is computed twice.
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_nonadv_xrows(Geo g, const T* __restrict__ W, const T* __restrict__ bface,
+                                                       T* __restrict__ F, StepArgs a, int rpb)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    using V = Vars<0>;
+    const size_t N = (size_t)g.n;
+    const int nx = g.nx;
+    int tid = threadIdx.x;
+    int r = tid / nx;
+    int i = tid - r * nx;
+    int row = blockIdx.x * rpb + r;
+    bool act = r < rpb && row < g.ny * g.nz;
+    int rowbase = row * nx;
+    Side<T> R;
+    if (act) {
+        int im2 = wrapc(i - 2, nx), im1 = wrapc(i - 1, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
+        T* mine = sm + (size_t)(r * nx + i) * 18;
+#pragma unroll
+        for (int v = 0; v < 6; v++) {
+            const T* q = W + (size_t)V::f[v] * N + rowbase;
+            Par<T> P = parabola(q[im2], q[im1], q[i], q[ip1], q[ip2]);
+            side_right(P, R, v);
+            mine[3 * v + 0] = P.qR;
+            mine[3 * v + 1] = P.dq;
+            mine[3 * v + 2] = P.q6;
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    int il = i == 0 ? nx - 1 : i - 1;
+    const T* left = sm + (size_t)(r * nx + il) * 18;
+    Side<T> L;
+#pragma unroll
+    for (int v = 0; v < 6; v++) {
+        L.e[v] = left[3 * v + 0];
+        L.dq[v] = left[3 * v + 1];
+        L.q6[v] = left[3 * v + 2];
+    }
+    int c = rowbase + i, cl = rowbase + il;
+    T out[7];
+    face_solve(W[cl], W[7 * N + cl], W[(size_t)V::f[3] * N + cl], W[(size_t)V::f[4] * N + cl],
+               W[c], W[7 * N + c], W[(size_t)V::f[3] * N + c], W[(size_t)V::f[4] * N + c],
+               bface[c], L, R, T(a.gamma), T(a.theta * (step_dt(a) / a.h)), out);
+    store_face(F, N, c, out);
+}
+
+// NONADV faces along D = y or z: each thread marches along one grid line over
+// a segment of `seg` faces with a sliding 5-cell window in registers, so each
+// cell's parabolas are computed once per segment (seg + 1 per seg faces);
+// threads are consecutive in x, so every load is coalesced.
+template <typename T, int D>
+__global__ __launch_bounds__(NTH) void k_nonadv_march(Geo g, const T* __restrict__ W, const T* __restrict__ bface,
+                                                      T* __restrict__ F, StepArgs a, int seg)
+{
+    using V = Vars<D>;
+    const size_t N = (size_t)g.n;
+    const int nd = D == 1 ? g.ny : g.nz;
+    const int no = D == 1 ? g.nz : g.ny;
+    const int nseg = (nd + seg - 1) / seg;
+    int t = blockIdx.x * NTH + threadIdx.x;
+    int i = t % g.nx;
+    int rest = t / g.nx;
+    int o = rest % no;
+    int sgi = rest / no;
+    if (sgi >= nseg) return;
+    const int base = D == 1 ? i + g.nxy * o : i + g.nx * o;
+    const int stride = D == 1 ? g.nx : g.nxy;
+    const int x0 = sgi * seg;
+    const int x1 = min(x0 + seg, nd);
+    const T gm = T(a.gamma);
+    const T ydx = T(a.theta * (step_dt(a) / a.h));
+
+    // window: w[v][m] = variable v of cell x-2+m; v = 0..5 parabola variables, 6 = rho
+    T w[7][5];
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        int cc = base + wrapc(x0 - 3 + m, nd) * stride;
+#pragma unroll
+        for (int v = 0; v < 6; v++) w[v][m] = W[(size_t)V::f[v] * N + cc];
+        w[6][m] = W[cc];
+    }
+    // parabolas of cell x0 - 1 (the left side of the first face)
+    Side<T> L;
+#pragma unroll
+    for (int v = 0; v < 6; v++) side_left(parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]), L, v);
+
+    for (int x = x0; x < x1; x++) {
+        int cn = base + wrapc(x + 2, nd) * stride;
+#pragma unroll
+        for (int v = 0; v < 7; v++) {
+#pragma unroll
+            for (int m = 0; m < 4; m++) w[v][m] = w[v][m + 1];
+            w[v][4] = W[(size_t)(v < 6 ? V::f[v] : 0) * N + cn];
+        }
+        Side<T> R, Ln;
+#pragma unroll
+        for (int v = 0; v < 6; v++) {
+            Par<T> P = parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]);
+            side_right(P, R, v);
+            side_left(P, Ln, v);
+        }
+        int c = base + x * stride;
+        T out[7];
+        // left cell x-1 is window slot 1, right cell x is slot 2
+        face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], bface[c], L, R, gm,
+                   ydx, out);
+        store_face(F, N, c, out);
+        L = Ln;
+    }
 }
 
 struct RK { double a, b; };
@@ -880,6 +1083,47 @@ int timing_collect(mhd_box* b)
     return MHD_OK;
 }
 
+// x faces: whole rows per block when a row fits one block, else one face per thread
+template <typename T>
+void launch_nonadv_x(mhd_box* b, const T* W, const T* bx, T* F, const StepArgs& a)
+{
+    const int nx = b->g.nx;
+    const int maxt = sizeof(T) == 8 ? 512 : 1024;
+    if (nx <= maxt) {
+        int rpb = nx >= 256 ? 1 : 256 / nx;
+        int threads = rpb * nx;
+        int rows = b->g.ny * b->g.nz;
+        int blocks = (rows + rpb - 1) / rpb;
+        size_t shm = (size_t)threads * 18 * sizeof(T);   // at most 72 KiB
+        if (threads <= 256) {
+            k_nonadv_xrows<T, 256><<<blocks, threads, shm, b->s>>>(b->g, W, bx, F, a, rpb);
+        } else if (threads <= 512) {
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nonadv_xrows<T, 512>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            k_nonadv_xrows<T, 512><<<blocks, threads, shm, b->s>>>(b->g, W, bx, F, a, rpb);
+        } else {
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nonadv_xrows<T, 1024>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            k_nonadv_xrows<T, 1024><<<blocks, threads, shm, b->s>>>(b->g, W, bx, F, a, rpb);
+        }
+    } else {
+        k_nonadv_face<T, 0><<<b->nblocks, NTH, 0, b->s>>>(b->g, W, bx, F, a);
+    }
+}
+
+constexpr int MARCH_SEG = 32;
+
+template <typename T, int D>
+void launch_nonadv_march(mhd_box* b, const T* W, const T* bf, T* F, const StepArgs& a)
+{
+    const int nd = D == 1 ? b->g.ny : b->g.nz;
+    const int no = D == 1 ? b->g.nz : b->g.ny;
+    int seg = nd < MARCH_SEG ? nd : MARCH_SEG;
+    long long threads = (long long)b->g.nx * no * ((nd + seg - 1) / seg);
+    int blocks = (int)((threads + NTH - 1) / NTH);
+    k_nonadv_march<T, D><<<blocks, NTH, 0, b->s>>>(b->g, W, bf, F, a, seg);
+}
+
 template <typename T>
 int nonadv_substage(mhd_box* b, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg, bool first)
 {
@@ -897,15 +1141,15 @@ int nonadv_substage(mhd_box* b, Slots sin, Slots sS, Slots sout, const StepArgs&
     }
     {
         KTimer t(b, MHD_K_NONADV_FACE);
-        k_nonadv_face<T, 0><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BX], F0, a);
+        launch_nonadv_x<T>(b, W, in.f[BX], F0, a);
     }
     {
         KTimer t(b, MHD_K_NONADV_FACE);
-        k_nonadv_face<T, 1><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BY], F1, a);
+        launch_nonadv_march<T, 1>(b, W, in.f[BY], F1, a);
     }
     {
         KTimer t(b, MHD_K_NONADV_FACE);
-        k_nonadv_face<T, 2><<<grid, blk, 0, b->s>>>(b->g, W, in.f[BZ], F2, a);
+        launch_nonadv_march<T, 2>(b, W, in.f[BZ], F2, a);
     }
     {
         KTimer t(b, MHD_K_NONADV_UPDATE);

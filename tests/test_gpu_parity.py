@@ -106,6 +106,19 @@ def test_ragged_non_cubic_box():
     assert_fields_close(box.get_state(), U, TOL64, "ragged")
 
 
+@pytest.mark.parametrize("shape", [(3, 2, 300), (2, 3, 520), (5, 40, 1), (40, 1, 3)])
+def test_face_kernel_dispatch_paths(shape):
+    # x rows longer than one 256-thread block, rows beyond the FP64 row-block
+    # limit (one face per thread), and lines shorter than the marching segment
+    W = inputs.white_noise(shape, seed=27, sigma=0.3, B=(0.2, -0.3, 0.1))
+    box, P, U = _pair(W)
+    for _ in range(2):
+        dt = oracle.cfl_dt(P, U)
+        box.step(dt)
+        oracle.step(P, U, dt)
+    assert_fields_close(box.get_state(), U, TOL64, "dispatch %s" % (shape,))
+
+
 @pytest.mark.parametrize("theta", [1.0, 0.0])
 def test_substage_right_hand_sides(theta):
     shape = (10, 14, 18)
