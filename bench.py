@@ -14,6 +14,7 @@ Workloads (synthetic, seeded; see paper_1608_08748_amd/inputs.py):
   c3  512^3 FP32 state (FP64 chemistry / reductions), rms Mach 5, beta 0.3,
       seed 3, with the FP64 run of the same seed and dt sequence for the error
   c1  32^3 FP64 white-noise box (the oracle's own configuration)
+  c5  serving: 256 boxes of {32..128}^3 with Poisson arrivals, p50/p99 latency
 
 Prints one JSON line.
 """
@@ -97,12 +98,70 @@ def _cpu_baseline(n=192, steps=3):
             % (n, steps, el)}
 
 
+def _serving_bench(args):
+    """c5: requests with sizes {32,48,64,96,128}^3, rms Mach U[1,10], beta
+    U[0.1,10], x_H2 log-uniform [1e-4,1e-1], 50 steps each, FP32 state with FP64
+    chemistry; saturated run (all at t = 0) for the capacity, then Poisson
+    arrivals at 0.8 of it for the latencies, then a 2 GB budget."""
+    import numpy as np
+    import torch
+    from paper_1608_08748_amd import binding, inputs, serving
+    steps = args.steps if args.steps is not None else 50
+    torch.cuda.set_device(0)
+    reqs = inputs.serving_requests(count=args.requests, seed=5)
+    t = time.perf_counter()
+    states = [inputs.request_state(r) for r in reqs]
+    gen_s = time.perf_counter() - t
+    mean_cells = float(np.mean([r["n"] ** 3 for r in reqs]))
+
+    def one(budget, slots, arrivals):
+        sv = binding.Server(budget, max_slots=slots, precision=binding.FP32_MIXED)
+        out = serving.run(sv, states, steps, arrivals=arrivals)
+        _, peak, cap = sv.memory()
+        sv.close()
+        torch.cuda.empty_cache()
+        out.pop("records")
+        out["peak_pool_bytes"] = peak
+        out["pool_bytes"] = cap
+        return out
+
+    # warm-up: a few requests through the merged kernels
+    sv = binding.Server(4 << 30, max_slots=8, precision=binding.FP32_MIXED)
+    serving.run(sv, states[:4], 2)
+    sv.close()
+    budget, slots = 64 << 30, 128
+    sat = one(budget, slots, None)
+    req_rate = 0.8 * sat["throughput"] / (mean_cells * steps)
+    arr = serving.poisson_arrivals(len(states), req_rate, seed=5)
+    poi = one(budget, slots, arr)
+    small = one(2 << 30, slots, None)
+    return {
+        "metric": METRIC, "value": round(poi["throughput"], 1), "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "c5: %d requests, boxes {32,48,64,96,128}^3, rms Mach U[1,10], beta U[0.1,10], "
+                               "x_H2 log-uniform [1e-4,1e-1], %d steps each, FP32 state + FP64 chemistry, "
+                               "Poisson arrivals at 0.8 x saturated capacity" % (len(states), steps),
+                   "hbm_budget_bytes": budget, "max_slots": slots, "parallelism": "single GPU, merged multi-box launches"},
+        "latency_p50_s": round(poi["latency_p50"], 4), "latency_p99_s": round(poi["latency_p99"], 4),
+        "arrival_rate_per_s": round(req_rate, 3),
+        "poisson": {k: poi[k] for k in ("throughput", "span_s", "rounds", "max_active", "statuses", "latency_mean",
+                                        "peak_pool_bytes")},
+        "saturated": {k: sat[k] for k in ("throughput", "span_s", "rounds", "max_active", "statuses",
+                                          "latency_p50", "latency_p99", "peak_pool_bytes")},
+        "budget_2GB": {k: small[k] for k in ("throughput", "span_s", "rounds", "max_active", "statuses",
+                                             "latency_p50", "latency_p99", "peak_pool_bytes", "pool_bytes")},
+        "ic_generation_s": round(gen_s, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,6 +173,10 @@ def main():
     import numpy as np
     import torch
     from paper_1608_08748_amd import binding
+
+    if args.config == "c5":
+        print(json.dumps(_serving_bench(args)), flush=True)
+        return
 
     cfg = _config(args.config)
     steps = args.steps if args.steps is not None else cfg["steps"]

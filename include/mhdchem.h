@@ -169,6 +169,83 @@ int mhd_destroy(mhd_box *b);
 
 const char *mhd_strerror(int status);
 
+/* ------------------------------------------------------------------ */
+/* Serving: many independent periodic boxes of uneven size share one GPU.
+ * Requests are admitted in arrival order as slots and workspace memory free
+ * up (the caller's workspace is the HBM budget; every box lives inside it),
+ * their state stays resident in HBM, and each call of mhd_server_progress
+ * advances every box in flight by one step of its own CFL dt with one merged
+ * launch per kernel of the step program for all boxes.  A box computes
+ * exactly the same bits alone or in any mix (same kernels, same per-box block
+ * decomposition and reductions).  Boxes use the server's physics parameters;
+ * n[0] <= 256.  Latencies are host wall-clock seconds since
+ * mhd_server_create. */
+
+typedef struct {
+    int32_t precision;       /* MHD_FP64 or MHD_FP32_MIXED                       */
+    double gamma, cfl, theta;
+    int32_t chemistry;
+    double n_unit_cm3, T_unit_K, t_unit_s;
+    int32_t max_slots;       /* boxes in flight at most, 1..1024                 */
+    void *stream;            /* hipStream_t; NULL = the null stream             */
+    void *workspace;         /* device memory, 256-byte aligned: the HBM budget */
+    size_t workspace_bytes;  /* (mhd_server_reserved_bytes of it hold the launch */
+                             /* tables, the rest is the box pool)                */
+} mhd_server_params;
+
+typedef struct {
+    int32_t n[3];            /* box cells along x, y, z                          */
+    int32_t steps;           /* steps to run                                      */
+    int32_t keep_state;      /* 1: keep the final conserved state for           */
+                             /*    mhd_server_result                              */
+} mhd_request;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;          /* MHD_OK or the box's latched fault                */
+    int32_t steps;           /* steps run                                         */
+    double t_submit, t_admit, t_done;   /* seconds since mhd_server_create       */
+    double totals[10];       /* conserved totals of the final state (FP64)      */
+    int64_t cells;
+    size_t bytes;            /* workspace bytes the box held                     */
+} mhd_completion;
+
+typedef struct mhd_server mhd_server;
+
+/* Workspace bytes a server keeps for its launch tables. */
+size_t mhd_server_reserved_bytes(void);
+
+/* Pool bytes one box of n cells takes (0 for invalid input). */
+size_t mhd_server_box_bytes(const mhd_server_params *p, const int32_t n[3]);
+
+/* Create a server on the caller's workspace and stream (pins a 32 MiB host
+ * staging buffer for the launch tables). */
+int mhd_server_create(const mhd_server_params *p, mhd_server **out);
+
+/* Queue a request with its primitive initial state (host FP64, the
+ * mhd_init_state layout; copied).  MHD_ENOMEM if the box can never fit the
+ * pool, MHD_EINVAL for bad sizes.  Does not touch the device. */
+int mhd_server_submit(mhd_server *s, const mhd_request *r, const double *prim, uint64_t *id);
+
+/* Admit queued requests while a slot and pool memory are free (first come,
+ * first served), run one merged step of every box in flight, wait for it, and
+ * retire the boxes that finished their steps (their memory is freed at once).
+ * Synchronises.  Outputs the numbers of boxes in flight and still queued. */
+int mhd_server_progress(mhd_server *s, int *n_active, int *n_pending);
+
+/* Take up to cap completion records (oldest first). */
+int mhd_server_poll(mhd_server *s, mhd_completion *out, int cap, int *n);
+
+/* Copy the final conserved state (10 fields, host FP64) of a finished request
+ * submitted with keep_state = 1; count must be 10 * cells.  Once per request. */
+int mhd_server_result(mhd_server *s, uint64_t id, double *cons_out, size_t count);
+
+/* Pool bytes in use now, the peak so far, and the pool size. */
+int mhd_server_memory(mhd_server *s, size_t *used, size_t *peak, size_t *capacity);
+
+/* Wait for the stream and release the server (not the workspace). */
+int mhd_server_destroy(mhd_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,41 @@ class MhdParams(ctypes.Structure):
     ]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("theta", ctypes.c_double),
+        ("chemistry", ctypes.c_int32),
+        ("n_unit_cm3", ctypes.c_double),
+        ("T_unit_K", ctypes.c_double),
+        ("t_unit_s", ctypes.c_double),
+        ("max_slots", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("steps", ctypes.c_int32), ("keep_state", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("totals", ctypes.c_double * 10),
+        ("cells", ctypes.c_int64),
+        ("bytes", ctypes.c_size_t),
+    ]
+
+
 class MhdError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
@@ -86,6 +121,16 @@ def lib():
         "mhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "mhd_set_timing": ([B, ctypes.c_int], ctypes.c_int),
         "mhd_get_timing": ([B, _D, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "mhd_server_reserved_bytes": ([], ctypes.c_size_t),
+        "mhd_server_box_bytes": ([ctypes.POINTER(ServerParams), ctypes.POINTER(ctypes.c_int32)], ctypes.c_size_t),
+        "mhd_server_create": ([ctypes.POINTER(ServerParams), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "mhd_server_submit": ([B, ctypes.POINTER(Request), _D, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "mhd_server_progress": ([B, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "mhd_server_poll": ([B, ctypes.POINTER(Completion), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "mhd_server_result": ([B, ctypes.c_uint64, _D, ctypes.c_size_t], ctypes.c_int),
+        "mhd_server_memory": ([B, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "mhd_server_destroy": ([B], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -201,6 +246,97 @@ class Box:
     def close(self):
         if getattr(self, "h", None):
             lib().mhd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_params(precision=FP32_MIXED, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None,
+                  max_slots=64):
+    p = ServerParams()
+    p.precision, p.gamma, p.cfl, p.theta = precision, gamma, cfl, theta
+    p.chemistry = 1 if chemistry else 0
+    p.n_unit_cm3, p.T_unit_K, p.t_unit_s = units if units is not None else DEFAULT_UNITS
+    p.max_slots = max_slots
+    return p
+
+
+def server_box_bytes(params, shape):
+    nz, ny, nx = shape
+    n = (ctypes.c_int32 * 3)(nx, ny, nz)
+    return lib().mhd_server_box_bytes(ctypes.byref(params), n)
+
+
+class Server:
+    """Continuous-batching server of many boxes on one GPU; ``budget_bytes`` of
+    device memory hold every box in flight (plus the fixed launch-table area)."""
+
+    def __init__(self, budget_bytes, max_slots=64, precision=FP32_MIXED, device="cuda", stream=None, **phys):
+        import torch
+        self.p = server_params(precision=precision, max_slots=max_slots, **phys)
+        total = int(budget_bytes) + lib().mhd_server_reserved_bytes()
+        self.ws = torch.empty(total, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        self.p.stream = self.stream.cuda_stream
+        self.p.workspace = self.ws.data_ptr()
+        self.p.workspace_bytes = total
+        h = ctypes.c_void_p()
+        _check(lib().mhd_server_create(ctypes.byref(self.p), ctypes.byref(h)), "mhd_server_create")
+        self.h = h
+        self.shapes = {}
+
+    def box_bytes(self, shape):
+        return server_box_bytes(self.p, shape)
+
+    def submit(self, W, steps, keep_state=False):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        shape = W.shape[1:]
+        r = Request()
+        r.n[0], r.n[1], r.n[2] = shape[2], shape[1], shape[0]
+        r.steps = int(steps)
+        r.keep_state = 1 if keep_state else 0
+        rid = ctypes.c_uint64()
+        _check(lib().mhd_server_submit(self.h, ctypes.byref(r), W.ctypes.data_as(_D), ctypes.byref(rid)),
+               "mhd_server_submit")
+        self.shapes[rid.value] = tuple(shape)
+        return rid.value
+
+    def progress(self):
+        na, npend = ctypes.c_int(), ctypes.c_int()
+        _check(lib().mhd_server_progress(self.h, ctypes.byref(na), ctypes.byref(npend)), "mhd_server_progress")
+        return na.value, npend.value
+
+    def poll(self, cap=1024):
+        buf = (Completion * cap)()
+        n = ctypes.c_int()
+        _check(lib().mhd_server_poll(self.h, buf, cap, ctypes.byref(n)), "mhd_server_poll")
+        out = []
+        for k in range(n.value):
+            c = buf[k]
+            out.append(dict(id=c.id, status=c.status, steps=c.steps, t_submit=c.t_submit, t_admit=c.t_admit,
+                            t_done=c.t_done, totals=np.array(c.totals[:]), cells=c.cells, bytes=c.bytes))
+        return out
+
+    def result(self, rid):
+        shape = self.shapes[rid]
+        U = np.empty((10,) + shape, dtype=np.float64)
+        _check(lib().mhd_server_result(self.h, ctypes.c_uint64(rid), U.ctypes.data_as(_D), U.size),
+               "mhd_server_result")
+        return U
+
+    def memory(self):
+        u, pk, cap = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().mhd_server_memory(self.h, ctypes.byref(u), ctypes.byref(pk), ctypes.byref(cap)),
+               "mhd_server_memory")
+        return u.value, pk.value, cap.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mhd_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

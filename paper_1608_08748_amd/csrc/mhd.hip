@@ -1,12 +1,10 @@
-// HIP implementation of one operator-split step of ideal MHD with H/H2
-// chemistry on a uniform periodic grid (Kulikov, Chernykh & Protasov,
-// arXiv:1608.08748), for AMD MI355X (gfx950).  C ABI: include/mhdchem.h.
+// Host runtime and C ABI (include/mhdchem.h) of the HIP implementation of one
+// operator-split step of ideal MHD with H/H2 chemistry on a uniform periodic
+// grid (Kulikov, Chernykh & Protasov, arXiv:1608.08748), for AMD MI355X.
 //
 // Stage names: NONADV is the paper's "eulerian" stage (Sec. 2.4, 2.5: pressure,
 // Lorentz force, p dV work, face-field update); ADV is its "lagrangian" stage
-// (Sec. 2.6: advection).  Readings of ambiguous passages are the same as the
-// ones listed in the design notes (dq = qR - qL, Step-4 blend weights, the
-// projector form of the face state, the pressure-gated dual-energy sync, ...).
+// (Sec. 2.6: advection).
 //
 // Data layout in HBM: structure of arrays, one array of n cells per field,
 // x fastest.  The state is split into three groups that are updated by
@@ -15,916 +13,28 @@
 //   M = (mx, my, mz, E, e)   updated by NONADV, ADV and the tail
 //   B = (bx, by, bz)         updated by NONADV (face-centred, lower faces)
 // so no stage copies a field it does not change.
+//
+// A step is a fixed program of kernel launches (mhd_kernels.hpp).  One box
+// sends the program to its stream; the server runs the same program for every
+// box in flight and merges the launches (one launch per program position over
+// all boxes), so a box gets the same bits alone or in a batch.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <new>
+#include <unordered_map>
+#include <vector>
 
+#include "mhd_kernels.hpp"
 #include "mhdchem.h"
 
-namespace {
+using namespace mhd;
 
-constexpr int NTH = 256;           // threads per block for cell-parallel kernels
-constexpr int NF = 10;             // conserved fields
-constexpr int NFACE = 7;           // per-face outputs
-enum { RHO = 0, MX, MY, MZ, EN, EI, BX, BY, BZ, H2 };
-
-// ---------------------------------------------------------------- geometry
-
-struct Geo {
-    int nx, ny, nz;
-    int nxy;
-    int n;          // nx * ny * nz
-};
-
-__device__ __forceinline__ int wrapc(int x, int n)
-{
-    if (x < 0) x += n;
-    if (x >= n) x -= n;
-    if ((unsigned)x >= (unsigned)n) {   // only for boxes thinner than the stencil
-        x %= n;
-        if (x < 0) x += n;
-    }
-    return x;
-}
-
-// cell index of the neighbour at offset s along direction D
-template <int D>
-__device__ __forceinline__ int nbr(const Geo& g, int c, int i, int j, int k, int s)
-{
-    if (D == 0) return c - i + wrapc(i + s, g.nx);
-    if (D == 1) return c + (wrapc(j + s, g.ny) - j) * g.nx;
-    return c + (wrapc(k + s, g.nz) - k) * g.nxy;
-}
-
-__device__ __forceinline__ void decompose(const Geo& g, int c, int& i, int& j, int& k)
-{
-    unsigned uc = (unsigned)c;
-    unsigned t = uc / (unsigned)g.nx;
-    i = (int)(uc - t * (unsigned)g.nx);
-    unsigned kk = t / (unsigned)g.ny;
-    j = (int)(t - kk * (unsigned)g.ny);
-    k = (int)kk;
-}
-
-template <typename T> struct Fields { T* f[NF]; };
-template <typename T> struct CFields { const T* f[NF]; };
-
-// ---------------------------------------------------------------- local parabola (Sec. 2.1)
-
-template <typename T> struct Par { T qL, qR, dq, q6; };
-
-// Step 1: limited central difference (min of the three candidates, sign of
-// the central difference; zero at extrema)
-template <typename T>
-__device__ __forceinline__ T limited_slope(T qm, T q0, T qp)
-{
-    T dq = T(0.5) * (qp - qm);
-    T a = T(2) * fabs(qp - q0);
-    T b = T(2) * fabs(q0 - qm);
-    T m = fmin(fmin(fabs(dq), a), b);
-    return ((qp - q0) * (q0 - qm) > T(0)) ? copysign(m, dq) : T(0);
-}
-
-// Step 1: fourth-order interface value q_{j+1/2} = 1/2 (q_j + q_{j+1}) - 1/6 (dm_{j+1} - dm_j)
-template <typename T>
-__device__ __forceinline__ T interface_value(T q0, T q1, T dm0, T dm1)
-{
-    return T(0.5) * (q0 + q1) - T(1.0 / 6.0) * (dm1 - dm0);
-}
-
-// margins that decide a saturated Step-4 weight without the division
-template <typename T> struct EtaMargin;
-template <> struct EtaMargin<double> { static constexpr double lo = 0.05 * (1.0 - 1e-9), hi = 0.1 * (1.0 + 1e-9); };
-template <> struct EtaMargin<float> { static constexpr float lo = 0.05f * (1.0f - 1e-5f), hi = 0.1f * (1.0f + 1e-5f); };
-
-// Steps 2-5 for cell j with line values qmm..qpp, Step-1 edge values qL, qR
-// and limited slope dm of the cell
-template <typename T>
-__device__ __forceinline__ Par<T> parabola_finish(T qmm, T qm, T q0, T qp, T qpp, T qL, T qR, T dm)
-{
-    // Step 2: monotone edge values
-    T dq = qR - qL;
-    T q6 = T(6) * (q0 - T(0.5) * (qL + qR));
-    bool flat = (qL - q0) * (q0 - qR) <= T(0);
-    bool overL = dq * q6 > dq * dq;
-    bool overR = dq * q6 < -(dq * dq);
-    T nL = flat ? q0 : (overL ? T(3) * q0 - T(2) * qR : qL);
-    T nR = flat ? q0 : ((!overL && overR) ? T(3) * q0 - T(2) * qL : qR);
-    // Step 4: discontinuity detector on second differences (h^2 cancels)
-    T qLp = q0 - T(0.25) * dm;
-    T qRp = q0 + T(0.25) * dm;
-    T Dm = q0 - T(2) * qm + qmm;
-    T Dp = qpp - T(2) * qp + q0;
-    T aqp = fabs(qp), aqm = fabs(qm);
-    T mn = fmin(fmin(aqp, aqm), aqp + aqm);
-    bool zero_eta = (fabs(qp - qm) - T(0.01) * mn <= T(0)) || (Dp * Dm > T(0));
-    // eta = t / d; the weight w = clamp(20 (eta - 0.05), 0, 1) is exactly 0
-    // or 1 outside a band around [0.05, 0.1], decided by products with a
-    // relative margin far above rounding; the division runs only inside it
-    T t = -(Dp - Dm);
-    T d = T(6) * (qp - qm);
-    T ts = d < T(0) ? -t : t;
-    T ds = fabs(d);
-    bool sat_hi = !zero_eta && ts >= EtaMargin<T>::hi * ds;
-    bool need = !zero_eta && !sat_hi && !(ts <= EtaMargin<T>::lo * ds);
-    T w = sat_hi ? T(1) : T(0);
-    if (need) {
-        T eta = t / d;
-        w = fmin(fmax(T(20) * (eta - T(0.05)), T(0)), T(1));
-    }
-    T fL = (T(1) - w) * nL + w * qLp;
-    T fR = (T(1) - w) * nR + w * qRp;
-    // Step 5
-    Par<T> p;
-    p.qL = fL;
-    p.qR = fR;
-    p.dq = fR - fL;
-    p.q6 = T(6) * (q0 - T(0.5) * (fL + fR));
-    return p;
-}
-
-// Steps 1-5 for the cell with line values qmm, qm, q0, qp, qpp
-template <typename T>
-__device__ __forceinline__ Par<T> parabola(T qmm, T qm, T q0, T qp, T qpp)
-{
-    T dm_m = limited_slope(qmm, qm, q0);
-    T dm_0 = limited_slope(qm, q0, qp);
-    T dm_p = limited_slope(q0, qp, qpp);
-    T qL = interface_value(qm, q0, dm_m, dm_0);
-    T qR = interface_value(q0, qp, dm_0, dm_p);
-    return parabola_finish(qmm, qm, q0, qp, qpp, qL, qR, dm_0);
-}
-
-// parabolas of the two cells on either side of a face from the 6-cell line
-// q0..q5 (cells i-3..i+2; left cell i-1, right cell i): the middle slopes and
-// the face value q_{i-1/2} are shared, so this is the same arithmetic as two
-// separate calls
-template <typename T>
-__device__ __forceinline__ void parabola_pair(T q0, T q1, T q2, T q3, T q4, T q5, Par<T>& PL, Par<T>& PR)
-{
-    T d1 = limited_slope(q0, q1, q2);
-    T d2 = limited_slope(q1, q2, q3);
-    T d3 = limited_slope(q2, q3, q4);
-    T d4 = limited_slope(q3, q4, q5);
-    T f12 = interface_value(q1, q2, d1, d2);
-    T f23 = interface_value(q2, q3, d2, d3);
-    T f34 = interface_value(q3, q4, d3, d4);
-    PL = parabola_finish(q0, q1, q2, q3, q4, f12, f23, d2);
-    PR = parabola_finish(q1, q2, q3, q4, q5, f23, f34, d3);
-}
-
-// Sec. 2.4: average over the right part of relative width y (the q(-nu t) formula)
-template <typename T>
-__device__ __forceinline__ T avg_right(const Par<T>& p, T y)
-{
-    return p.qR - T(0.5) * y * (p.dq - p.q6 * (T(1) - T(2.0 / 3.0) * y));
-}
-
-// Sec. 2.4: average over the left part of relative width y (the q(+nu t) formula)
-template <typename T>
-__device__ __forceinline__ T avg_left(const Par<T>& p, T y)
-{
-    return p.qL + T(0.5) * y * (p.dq + p.q6 * (T(1) - T(2.0 / 3.0) * y));
-}
-
-template <typename T> struct Eps;
-template <> struct Eps<double> { static constexpr double v = 1e-12; };
-template <> struct Eps<float> { static constexpr float v = 1e-6f; };
-
-// ---------------------------------------------------------------- kernels
-
-struct StepArgs {
-    double dt_val;          // explicit step, or
-    const double* dt_dev;   // device-resident CFL step when non-null
-    double gamma;
-    double h;               // 1 / nx
-    double theta;
-    double cfl_tol;         // relative slack of the dt <= CFL-bound check
-};
-
-__device__ __forceinline__ double step_dt(const StepArgs& a)
-{
-    return a.dt_dev ? *a.dt_dev : a.dt_val;
-}
-
-// primitive state of every cell: rho, vx, vy, vz, Bcx, Bcy, Bcz, p
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_prim(Geo g, CFields<T> U, T* __restrict__ W, StepArgs a,
-                                              uint32_t* flags, const double* dt_cfl)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c == 0 && dt_cfl && !a.dt_dev) {
-        if (a.dt_val > *dt_cfl * (1.0 + a.cfl_tol)) atomicOr(flags, 2u);
-    }
-    if (c >= g.n) return;
-    int i, j, k;
-    decompose(g, c, i, j, k);
-    const size_t N = (size_t)g.n;
-    T rho = U.f[RHO][c];
-    W[0 * N + c] = rho;
-    W[1 * N + c] = U.f[MX][c] / rho;
-    W[2 * N + c] = U.f[MY][c] / rho;
-    W[3 * N + c] = U.f[MZ][c] / rho;
-    W[4 * N + c] = T(0.5) * (U.f[BX][c] + U.f[BX][nbr<0>(g, c, i, j, k, 1)]);
-    W[5 * N + c] = T(0.5) * (U.f[BY][c] + U.f[BY][nbr<1>(g, c, i, j, k, 1)]);
-    W[6 * N + c] = T(0.5) * (U.f[BZ][c] + U.f[BZ][nbr<2>(g, c, i, j, k, 1)]);
-    W[7 * N + c] = T(a.gamma - 1.0) * U.f[EI][c];
-}
-
-// What one side of a face needs from a cell's parabolas (6 variables): the
-// edge value facing the face (qR of the left cell, qL of the right cell), dq
-// and q6.
-template <typename T> struct Side { T e[6], dq[6], q6[6]; };
-
-template <typename T>
-__device__ __forceinline__ void side_left(const Par<T>& P, Side<T>& S, int v)
-{
-    S.e[v] = P.qR;
-    S.dq[v] = P.dq;
-    S.q6[v] = P.q6;
-}
-
-template <typename T>
-__device__ __forceinline__ void side_right(const Par<T>& P, Side<T>& S, int v)
-{
-    S.e[v] = P.qL;
-    S.dq[v] = P.dq;
-    S.q6[v] = P.q6;
-}
-
-// NONADV face state (Sec. 2.4) of one face and the fluxes and edge-field
-// contributions it produces.  Inputs: cell-centre rho, p, Bt1, Bt2 of the left
-// and right cells, the face normal field bn, the two sides' parabolas of
-// (vn, vt1, vt2, Bt1, Bt2, p).  Outputs (7): momentum flux (normal, t1, t2),
-// energy flux, face normal velocity, E along t1 (B_t2 U_n - B_n U_t2), E along
-// t2 (B_n U_t1 - B_t1 U_n).
-template <typename T>
-__device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr, T b1r, T b2r, T bn,
-                                           const Side<T>& L, const Side<T>& R, T gm, T ydx, T out[7])
-{
-    const T eps = Eps<T>::v;
-    // face averages (sqrt(rho) weights; cross weights for Bt)
-    T sl = sqrt(rl), sr = sqrt(rr);
-    T iw = T(1) / (sl + sr);
-    T rho = (sl * rl + sr * rr) * iw;
-    T p = (sl * pl + sr * pr) * iw;
-    T bt1 = (sl * b1r + sr * b1l) * iw;
-    T bt2 = (sl * b2r + sr * b2l) * iw;
-
-    // eigen-structure (Sec. 2.3, 2.4, eigenvector appendix)
-    T irho = T(1) / rho;
-    T c2 = gm * p * irho;
-    T ca2 = bn * bn * irho;
-    T b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) * irho;
-    T s = c2 + b2;
-    T disc = fmax(s * s - T(4) * c2 * ca2, T(0));
-    T sd = sqrt(disc);
-    T cf2 = T(0.5) * (s + sd);
-    T cs2 = fmax(T(0.5) * (s - sd), T(0));
-    T cc = sqrt(c2), ca = sqrt(ca2), cf = sqrt(cf2), cs = sqrt(cs2);
-    const T r2i = T(0.70710678118654752440);
-    T den = cf2 - cs2;
-    T af = r2i, as = r2i;
-    if (den > eps * s) {
-        T iden = T(1) / den;
-        af = sqrt(fmax(c2 - cs2, T(0)) * iden);
-        as = sqrt(fmax(cf2 - c2, T(0)) * iden);
-    }
-    T by = r2i, bz = r2i;
-    T btsq = bt1 * bt1 + bt2 * bt2;
-    if (btsq > eps * (bn * bn + btsq + gm * p)) {
-        T ibt = T(1) / sqrt(btsq);
-        by = bt1 * ibt;
-        bz = bt2 * ibt;
-    }
-    T sg = bn >= T(0) ? T(1) : T(-1);
-    T srho = sqrt(rho);
-
-    // parabola averages on the upwind side of each wave: waves +cf, +cs, +ca
-    // read the left cell (right part, q(-nu t)), waves -cf, -cs, -ca the right
-    // cell (left part, q(+nu t))
-    T qf[6], qfm[6], qs[6], qsm[6], qa[6], qam[6];
-    T y3[3] = { ydx * cf, ydx * cs, ydx * ca };
-    T hy[3], ky[3];
-#pragma unroll
-    for (int w = 0; w < 3; w++) {
-        hy[w] = T(0.5) * y3[w];
-        ky[w] = T(1) - T(2.0 / 3.0) * y3[w];
-    }
-#pragma unroll
-    for (int v = 0; v < 6; v++) {
-        qf[v] = L.e[v] - hy[0] * (L.dq[v] - L.q6[v] * ky[0]);
-        qs[v] = L.e[v] - hy[1] * (L.dq[v] - L.q6[v] * ky[1]);
-        qa[v] = L.e[v] - hy[2] * (L.dq[v] - L.q6[v] * ky[2]);
-        qfm[v] = R.e[v] + hy[0] * (R.dq[v] + R.q6[v] * ky[0]);
-        qsm[v] = R.e[v] + hy[1] * (R.dq[v] + R.q6[v] * ky[1]);
-        qam[v] = R.e[v] + hy[2] * (R.dq[v] + R.q6[v] * ky[2]);
-    }
-
-    // characteristic amplitudes s_k = l_k . q_up(k)
-    T ic2 = T(1) / c2;
-    T isc = T(1) / (srho * cc);
-    T A = T(0.5) * ic2;                  // 1 / (2 c^2)
-    T Bc = T(0.5) * isc;                 // 1 / (2 sqrt(rho) c)
-    T Cc = A * irho;                     // 1 / (2 rho c^2)
-    T Dc = r2i / srho;                   // 1 / sqrt(2 rho)
-    T afcf = af * cf, ascs = as * cs;
-    auto vtb = [&](const T* q) { return by * q[1] + bz * q[2]; };
-    auto btb = [&](const T* q) { return by * q[3] + bz * q[4]; };
-    auto vtp = [&](const T* q) { return -bz * q[1] + by * q[2]; };
-    auto btp = [&](const T* q) { return -bz * q[3] + by * q[4]; };
-    T s0 = (afcf * qf[0] - ascs * sg * vtb(qf)) * A + as * btb(qf) * Bc + af * qf[5] * Cc;
-    T s1 = (-afcf * qfm[0] + ascs * sg * vtb(qfm)) * A + as * btb(qfm) * Bc + af * qfm[5] * Cc;
-    T s2 = (ascs * qs[0] + afcf * sg * vtb(qs)) * A - af * btb(qs) * Bc + as * qs[5] * Cc;
-    T s3 = (-ascs * qsm[0] - afcf * sg * vtb(qsm)) * A - af * btb(qsm) * Bc + as * qsm[5] * Cc;
-    T s4 = sg * r2i * vtp(qa) - btp(qa) * Dc;
-    T s5 = sg * r2i * vtp(qam) + btp(qam) * Dc;
-
-    // face state q = sum_k r_k s_k
-    T fdm = s0 - s1, fsm = s0 + s1, sdm = s2 - s3, ssm = s2 + s3, adm = s4 - s5, asm_ = s4 + s5;
-    T src = srho * cc;
-    T sr2 = r2i * srho;
-    T gp = gm * p;
-    T Vn = afcf * fdm + ascs * sdm;
-    T Vt1 = sg * by * (-ascs * fdm + afcf * sdm) - bz * sg * r2i * asm_;
-    T Vt2 = sg * bz * (-ascs * fdm + afcf * sdm) + by * sg * r2i * asm_;
-    T Bt1 = by * src * (as * fsm - af * ssm) + sr2 * bz * adm;
-    T Bt2 = bz * src * (as * fsm - af * ssm) - sr2 * by * adm;
-    T P = gp * (af * fsm + as * ssm);
-
-    // fluxes of the non-advective equations and edge-field contributions
-    T Pst = P + T(0.5) * (bn * bn + Bt1 * Bt1 + Bt2 * Bt2);
-    T BV = bn * Vn + Bt1 * Vt1 + Bt2 * Vt2;
-    out[0] = Pst - bn * bn;
-    out[1] = -(bn * Bt1);
-    out[2] = -(bn * Bt2);
-    out[3] = Pst * Vn - bn * BV;
-    out[4] = Vn;
-    out[5] = Bt2 * Vn - bn * Vt2;
-    out[6] = bn * Vt1 - Bt1 * Vn;
-}
-
-// primitive-array slots of the six parabola variables for faces along D:
-// (vn, vt1, vt2, Bt1, Bt2, p) in the W layout rho, vx, vy, vz, Bcx, Bcy, Bcz, p
-template <int D> struct Vars {
-    static constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-    static constexpr int f[6] = { 1 + D, 1 + T1, 1 + T2, 4 + T1, 4 + T2, 7 };
-};
-
-template <typename T>
-__device__ __forceinline__ void store_face(T* __restrict__ F, size_t N, int c, const T out[7])
-{
-#pragma unroll
-    for (int q = 0; q < 7; q++) F[q * N + c] = out[q];
-}
-
-// NONADV faces along D, one face per thread, both adjacent parabolas computed
-// by the thread (general fallback for any box)
-template <typename T, int D>
-__global__ __launch_bounds__(NTH) void k_nonadv_face(Geo g, const T* __restrict__ W, const T* __restrict__ bface,
-                                                     T* __restrict__ F, StepArgs a)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    using V = Vars<D>;
-    int i, j, k;
-    decompose(g, c, i, j, k);
-    const size_t N = (size_t)g.n;
-    int idx[6];
-#pragma unroll
-    for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
-    Side<T> L, R;
-#pragma unroll
-    for (int v = 0; v < 6; v++) {
-        const T* q = W + (size_t)V::f[v] * N;
-        Par<T> PL, PR;
-        parabola_pair(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], PL, PR);
-        side_left(PL, L, v);
-        side_right(PR, R, v);
-    }
-    T out[7];
-    face_solve(W[idx[2]], W[7 * N + idx[2]], W[(size_t)V::f[3] * N + idx[2]], W[(size_t)V::f[4] * N + idx[2]],
-               W[idx[3]], W[7 * N + idx[3]], W[(size_t)V::f[3] * N + idx[3]], W[(size_t)V::f[4] * N + idx[3]],
-               bface[c], L, R, T(a.gamma), T(a.theta * (step_dt(a) / a.h)), out);
-    store_face(F, N, c, out);
-}
-
-// NONADV faces along x with whole x rows per block: each thread computes the
-// parabolas of its own cell once; the left neighbour's side comes from LDS
-// (periodic wrap inside the row), so no parabola is computed twice.
-template <typename T, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_nonadv_xrows(Geo g, const T* __restrict__ W, const T* __restrict__ bface,
-                                                       T* __restrict__ F, StepArgs a, int rpb)
-{
-    extern __shared__ unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
-    using V = Vars<0>;
-    const size_t N = (size_t)g.n;
-    const int nx = g.nx;
-    int tid = threadIdx.x;
-    int r = tid / nx;
-    int i = tid - r * nx;
-    int row = blockIdx.x * rpb + r;
-    bool act = r < rpb && row < g.ny * g.nz;
-    int rowbase = row * nx;
-    Side<T> R;
-    if (act) {
-        int im2 = wrapc(i - 2, nx), im1 = wrapc(i - 1, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
-        T* mine = sm + (size_t)(r * nx + i) * 18;
-#pragma unroll
-        for (int v = 0; v < 6; v++) {
-            const T* q = W + (size_t)V::f[v] * N + rowbase;
-            Par<T> P = parabola(q[im2], q[im1], q[i], q[ip1], q[ip2]);
-            side_right(P, R, v);
-            mine[3 * v + 0] = P.qR;
-            mine[3 * v + 1] = P.dq;
-            mine[3 * v + 2] = P.q6;
-        }
-    }
-    __syncthreads();
-    if (!act) return;
-    int il = i == 0 ? nx - 1 : i - 1;
-    const T* left = sm + (size_t)(r * nx + il) * 18;
-    Side<T> L;
-#pragma unroll
-    for (int v = 0; v < 6; v++) {
-        L.e[v] = left[3 * v + 0];
-        L.dq[v] = left[3 * v + 1];
-        L.q6[v] = left[3 * v + 2];
-    }
-    int c = rowbase + i, cl = rowbase + il;
-    T out[7];
-    face_solve(W[cl], W[7 * N + cl], W[(size_t)V::f[3] * N + cl], W[(size_t)V::f[4] * N + cl],
-               W[c], W[7 * N + c], W[(size_t)V::f[3] * N + c], W[(size_t)V::f[4] * N + c],
-               bface[c], L, R, T(a.gamma), T(a.theta * (step_dt(a) / a.h)), out);
-    store_face(F, N, c, out);
-}
-
-// NONADV faces along D = y or z: each thread marches along one grid line over
-// a segment of `seg` faces with a sliding 5-cell window in registers, so each
-// cell's parabolas are computed once per segment (seg + 1 per seg faces);
-// threads are consecutive in x, so every load is coalesced.
-template <typename T, int D>
-__global__ __launch_bounds__(NTH) void k_nonadv_march(Geo g, const T* __restrict__ W, const T* __restrict__ bface,
-                                                      T* __restrict__ F, StepArgs a, int seg)
-{
-    using V = Vars<D>;
-    const size_t N = (size_t)g.n;
-    const int nd = D == 1 ? g.ny : g.nz;
-    const int no = D == 1 ? g.nz : g.ny;
-    const int nseg = (nd + seg - 1) / seg;
-    int t = blockIdx.x * NTH + threadIdx.x;
-    int i = t % g.nx;
-    int rest = t / g.nx;
-    int o = rest % no;
-    int sgi = rest / no;
-    if (sgi >= nseg) return;
-    const int base = D == 1 ? i + g.nxy * o : i + g.nx * o;
-    const int stride = D == 1 ? g.nx : g.nxy;
-    const int x0 = sgi * seg;
-    const int x1 = min(x0 + seg, nd);
-    const T gm = T(a.gamma);
-    const T ydx = T(a.theta * (step_dt(a) / a.h));
-
-    // window: w[v][m] = variable v of cell x-2+m; v = 0..5 parabola variables, 6 = rho
-    T w[7][5];
-#pragma unroll
-    for (int m = 0; m < 5; m++) {
-        int cc = base + wrapc(x0 - 3 + m, nd) * stride;
-#pragma unroll
-        for (int v = 0; v < 6; v++) w[v][m] = W[(size_t)V::f[v] * N + cc];
-        w[6][m] = W[cc];
-    }
-    // parabolas of cell x0 - 1 (the left side of the first face)
-    Side<T> L;
-#pragma unroll
-    for (int v = 0; v < 6; v++) side_left(parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]), L, v);
-
-    for (int x = x0; x < x1; x++) {
-        int cn = base + wrapc(x + 2, nd) * stride;
-#pragma unroll
-        for (int v = 0; v < 7; v++) {
-#pragma unroll
-            for (int m = 0; m < 4; m++) w[v][m] = w[v][m + 1];
-            w[v][4] = W[(size_t)(v < 6 ? V::f[v] : 0) * N + cn];
-        }
-        Side<T> R, Ln;
-#pragma unroll
-        for (int v = 0; v < 6; v++) {
-            Par<T> P = parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]);
-            side_right(P, R, v);
-            side_left(P, Ln, v);
-        }
-        int c = base + x * stride;
-        T out[7];
-        // left cell x-1 is window slot 1, right cell x is slot 2
-        face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], bface[c], L, R, gm,
-                   ydx, out);
-        store_face(F, N, c, out);
-        L = Ln;
-    }
-}
-
-struct RK { double a, b; };
-
-// NONADV update: flux differences, p dV work, face-field update from edge
-// fields (Sec. 2.5), Runge-Kutta combination (Sec. 2.2).  debug_inc != 0
-// writes tau R(U) instead of the combination.
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_nonadv_update(Geo g, CFields<T> U, CFields<T> S, Fields<T> O,
-                                                       const T* __restrict__ Fx, const T* __restrict__ Fy,
-                                                       const T* __restrict__ Fz, StepArgs a, RK rk, int debug_inc)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    int i, j, k;
-    decompose(g, c, i, j, k);
-    const size_t N = (size_t)g.n;
-    const T dtdx = T(step_dt(a) / a.h);
-    int xp = nbr<0>(g, c, i, j, k, 1), xm = nbr<0>(g, c, i, j, k, -1);
-    int yp = nbr<1>(g, c, i, j, k, 1), ym = nbr<1>(g, c, i, j, k, -1);
-    int zp = nbr<2>(g, c, i, j, k, 1), zm = nbr<2>(g, c, i, j, k, -1);
-    const T* Fd[3] = { Fx, Fy, Fz };
-    int up[3] = { xp, yp, zp };
-    T dF[3][5];
-#pragma unroll
-    for (int d = 0; d < 3; d++)
-#pragma unroll
-        for (int v = 0; v < 5; v++) dF[d][v] = Fd[d][v * N + up[d]] - Fd[d][v * N + c];
-    T inc[NF];
-    // momentum component a takes slot (a - d) mod 3 from direction d
-    inc[MX] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
-    inc[MY] = -dtdx * ((dF[0][1] + dF[1][0]) + dF[2][2]);
-    inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
-    inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
-    T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
-    inc[EI] = -T(a.gamma - 1.0) * U.f[EI][c] * dtdx * divv;
-
-    // edge fields (electric-field appendix): Ex at (i, j-1/2, k-1/2) from
-    // z faces at j-1, j and y faces at k, k-1; Ey at (i-1/2, j, k-1/2) from
-    // z faces at i-1, i and x faces at k-1, k; Ez at (i-1/2, j-1/2, k) from
-    // x faces at j-1, j and y faces at i-1, i.
-    const T* ezx = Fz + 5 * N;   // z faces, E along x
-    const T* ezy = Fz + 6 * N;   // z faces, E along y
-    const T* eyz = Fy + 5 * N;   // y faces, E along z
-    const T* eyx = Fy + 6 * N;   // y faces, E along x
-    const T* exy = Fx + 5 * N;   // x faces, E along y
-    const T* exz = Fx + 6 * N;   // x faces, E along z
-    auto Ex = [&](int cc, int cym, int czm) { return T(0.25) * (((ezx[cym] + ezx[cc]) + eyx[cc]) + eyx[czm]); };
-    auto Ey = [&](int cc, int cxm, int czm) { return T(0.25) * (((ezy[cxm] + ezy[cc]) + exy[czm]) + exy[cc]); };
-    auto Ez = [&](int cc, int cym, int cxm) { return T(0.25) * (((exz[cym] + exz[cc]) + eyz[cxm]) + eyz[cc]); };
-    // neighbours of the shifted cells
-    int ip, jp, kp;
-    // Ex at c, c+y, c+z
-    T Ex_c = Ex(c, ym, zm);
-    decompose(g, yp, ip, jp, kp);
-    T Ex_yp = Ex(yp, c, nbr<2>(g, yp, ip, jp, kp, -1));
-    decompose(g, zp, ip, jp, kp);
-    T Ex_zp = Ex(zp, nbr<1>(g, zp, ip, jp, kp, -1), c);
-    // Ey at c, c+x, c+z
-    T Ey_c = Ey(c, xm, zm);
-    decompose(g, xp, ip, jp, kp);
-    T Ey_xp = Ey(xp, c, nbr<2>(g, xp, ip, jp, kp, -1));
-    decompose(g, zp, ip, jp, kp);
-    T Ey_zp = Ey(zp, nbr<0>(g, zp, ip, jp, kp, -1), c);
-    // Ez at c, c+x, c+y
-    T Ez_c = Ez(c, ym, xm);
-    decompose(g, xp, ip, jp, kp);
-    T Ez_xp = Ez(xp, nbr<1>(g, xp, ip, jp, kp, -1), c);
-    decompose(g, yp, ip, jp, kp);
-    T Ez_yp = Ez(yp, c, nbr<0>(g, yp, ip, jp, kp, -1));
-    inc[BX] = -dtdx * (Ez_yp - Ez_c) + dtdx * (Ey_zp - Ey_c);
-    inc[BY] = -dtdx * (Ex_zp - Ex_c) + dtdx * (Ez_xp - Ez_c);
-    inc[BZ] = -dtdx * (Ey_xp - Ey_c) + dtdx * (Ex_yp - Ex_c);
-
-    const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
-    if (debug_inc) {
-#pragma unroll
-        for (int q = 0; q < 8; q++) O.f[upd[q]][c] = inc[upd[q]];
-        O.f[RHO][c] = T(0);
-        O.f[H2][c] = T(0);
-        return;
-    }
-    const T ra = T(rk.a), rb = T(rk.b);
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-        int f = upd[q];
-        T u = U.f[f][c];
-        O.f[f][c] = (u + ra * (S.f[f][c] - u)) + rb * inc[f];
-    }
-}
-
-// ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, 7 x N,
-// in the order rho, mx, my, mz, E, e, h2.
-template <typename T, int D>
-__global__ __launch_bounds__(NTH) void k_adv_face(Geo g, CFields<T> U, T* __restrict__ F, StepArgs a)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    int i, j, k;
-    decompose(g, c, i, j, k);
-    const size_t N = (size_t)g.n;
-    const T ydx = T(a.theta * (step_dt(a) / a.h));
-    int idx[6];
-#pragma unroll
-    for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
-    T rl = U.f[RHO][idx[2]], rr = U.f[RHO][c];
-    T vl = U.f[MX + D][idx[2]] / rl;
-    T vr = U.f[MX + D][c] / rr;
-    T sl = sqrt(rl), sr = sqrt(rr);
-    T vf = (sl * vl + sr * vr) / (sl + sr);
-    bool upw = vf >= T(0);
-    T y = upw ? ydx * vf : ydx * (-vf);
-    const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
-#pragma unroll
-    for (int q = 0; q < 7; q++) {
-        const T* u = U.f[fld[q]];
-        int o = upw ? 0 : 1;
-        T q0 = u[idx[o]], q1 = u[idx[o + 1]], q2 = u[idx[o + 2]], q3 = u[idx[o + 3]], q4 = u[idx[o + 4]];
-        Par<T> P = parabola(q0, q1, q2, q3, q4);
-        T qup = upw ? avg_right(P, y) : avg_left(P, y);
-        F[q * N + c] = vf * qup;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_adv_update(Geo g, CFields<T> U, CFields<T> S, Fields<T> O,
-                                                    const T* __restrict__ Fx, const T* __restrict__ Fy,
-                                                    const T* __restrict__ Fz, StepArgs a, RK rk, int debug_inc)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    int i, j, k;
-    decompose(g, c, i, j, k);
-    const size_t N = (size_t)g.n;
-    const T dtdx = T(step_dt(a) / a.h);
-    int xp = nbr<0>(g, c, i, j, k, 1), yp = nbr<1>(g, c, i, j, k, 1), zp = nbr<2>(g, c, i, j, k, 1);
-    const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
-    const T ra = T(rk.a), rb = T(rk.b);
-#pragma unroll
-    for (int q = 0; q < 7; q++) {
-        T dx = Fx[q * N + xp] - Fx[q * N + c];
-        T dy = Fy[q * N + yp] - Fy[q * N + c];
-        T dz = Fz[q * N + zp] - Fz[q * N + c];
-        T inc = -dtdx * ((dx + dy) + dz);
-        int f = fld[q];
-        if (debug_inc) {
-            O.f[f][c] = inc;
-        } else {
-            T u = U.f[f][c];
-            O.f[f][c] = (u + ra * (S.f[f][c] - u)) + rb * inc;
-        }
-    }
-    if (debug_inc) {
-        O.f[BX][c] = T(0);
-        O.f[BY][c] = T(0);
-        O.f[BZ][c] = T(0);
-    }
-}
-
-// ---------------------------------------------------------------- FP64 per-cell physics
-
-struct ChemArgs {
-    int on;
-    double n_unit, T_unit, t_unit;
-};
-
-// Sec. 2.7 with the appendix rates of reactions 1-4 (optically thin k4)
-__device__ double chem_h2(const ChemArgs& ch, double gamma, double rho, double e, double h2, double dt)
-{
-    double p = (gamma - 1.0) * e;
-    double xh2 = h2 / rho;
-    double mu = 1.0 / (1.0 - 0.5 * xh2);
-    double T = ch.T_unit * mu * p / rho;
-    double nH = ch.n_unit * (rho - h2);
-    double nH2 = ch.n_unit * h2 / 2.0;
-    double n = nH + nH2;
-    double t2 = T / 100.0;
-    double st2 = sqrt(t2);
-    double k1b = 3e-17 * st2 / (1.0 + 0.4 * st2 + 0.2 * t2 + 0.08 * t2 * t2);
-    double k2 = (T > 7390.0) ? 6.11e-14 * exp(-2.93e4 / T) : 2.67e-15 * exp(-(6750.0 / T) * (6750.0 / T));
-    double k3 = (T > 7291.0) ? 5.22e-14 * exp(-3.22e4 / T)
-                             : 3.17e-15 * exp(-(4060.0 / T) - (7500.0 / T) * (7500.0 / T));
-    double k4 = 3.3 * 1.7e-11;
-    double C = k1b * n * nH;
-    double Dd = k2 * nH + k3 * nH2 + k4;
-    double ts = dt * ch.t_unit;
-    double nn = nH2 + ts * (C - Dd * nH2) / (1.0 + ts * Dd);
-    double nmax = ch.n_unit * rho / 2.0;
-    nn = nn > nmax ? nmax : nn;
-    nn = nn < 0.0 ? 0.0 : nn;
-    return 2.0 * nn / ch.n_unit;
-}
-
-// Sec. 2.3: the speed sum of the CFL rule for one cell (FP64)
-__device__ double cell_speed(double gamma, double rho, double mx, double my, double mz, double e, double bx,
-                             double by, double bz)
-{
-    double vx = mx / rho, vy = my / rho, vz = mz / rho;
-    double v = sqrt(vx * vx + vy * vy + vz * vz);
-    double p = (gamma - 1.0) * e;
-    double c2 = gamma * p / rho;
-    double ca2 = bx * bx / rho;
-    double b2 = (bx * bx + by * by + bz * bz) / rho;
-    double s = c2 + b2;
-    double disc = s * s - 4.0 * c2 * ca2;
-    disc = disc < 0.0 ? 0.0 : disc;
-    double sd = sqrt(disc);
-    double cf2 = 0.5 * (s + sd);
-    double cs2 = 0.5 * (s - sd);
-    cs2 = cs2 < 0.0 ? 0.0 : cs2;
-    return v + sqrt(b2) + sqrt(c2) + sqrt(ca2) + sqrt(cs2) + sqrt(cf2);
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ void block_max_store(double v, double* out)
-{
-    __shared__ double red[NTH / 64];
-    v = wave_max(v);
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0];
-        for (int w = 1; w < NTH / 64; w++) m = red[w] > m ? red[w] : m;
-        out[blockIdx.x] = m;
-    }
-}
-
-// Tail of the step (after ADV): H2 clamp to [0, rho], chemistry, dual-energy
-// sync (Sec. 2.8, pressure-gated), validity flag, per-block CFL speed maximum.
-// mode: 1 = full tail, 0 = speed only (state unchanged).
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_tail(Geo g, Fields<T> U, StepArgs a, ChemArgs ch, int mode,
-                                              double* __restrict__ part, uint32_t* flags)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    double spd = 0.0;
-    if (c < g.n) {
-        int i, j, k;
-        decompose(g, c, i, j, k);
-        double rho = (double)U.f[RHO][c];
-        double mx = (double)U.f[MX][c], my = (double)U.f[MY][c], mz = (double)U.f[MZ][c];
-        double E = (double)U.f[EN][c];
-        double e = (double)U.f[EI][c];
-        double bx = 0.5 * ((double)U.f[BX][c] + (double)U.f[BX][nbr<0>(g, c, i, j, k, 1)]);
-        double by = 0.5 * ((double)U.f[BY][c] + (double)U.f[BY][nbr<1>(g, c, i, j, k, 1)]);
-        double bz = 0.5 * ((double)U.f[BZ][c] + (double)U.f[BZ][nbr<2>(g, c, i, j, k, 1)]);
-        if (mode == 1) {
-            double h2 = (double)U.f[H2][c];
-            h2 = h2 > rho ? rho : h2;
-            h2 = h2 < 0.0 ? 0.0 : h2;
-            if (ch.on) h2 = chem_h2(ch, a.gamma, rho, e, h2, step_dt(a));
-            double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
-            double M = 0.5 * (bx * bx + by * by + bz * bz);
-            double ei = E - K - M;
-            if (ei >= 1e-3 * E && (a.gamma - 1.0) * ei > M) e = ei;
-            U.f[H2][c] = (T)h2;
-            U.f[EI][c] = (T)e;
-            e = (double)(T)e;
-        }
-        bool ok = rho > 0.0 && e > 0.0 && isfinite(rho) && isfinite(e) && isfinite(E) && isfinite(mx) &&
-                  isfinite(my) && isfinite(mz) && isfinite(bx) && isfinite(by) && isfinite(bz);
-        if (!ok) atomicOr(flags, 1u);
-        spd = ok ? cell_speed(a.gamma, rho, mx, my, mz, e, bx, by, bz) : 0.0;
-    }
-    block_max_store(spd, part);
-}
-
-// dt = cfl h / max speed over the per-block maxima (max is exact, so the
-// result equals the minimum over cells of cfl h / speed)
-__global__ __launch_bounds__(1024) void k_reduce_dt(const double* __restrict__ part, int nparts, double cflh,
-                                                    double* __restrict__ dt)
-{
-    __shared__ double red[16];
-    double m = 0.0;
-    for (int t = threadIdx.x; t < nparts; t += 1024) m = part[t] > m ? part[t] : m;
-    m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = red[0];
-        for (int w = 1; w < 16; w++) r = red[w] > r ? red[w] : r;
-        *dt = r > 0.0 ? cflh / r : 0.0;
-    }
-}
-
-// FP64 totals: per-block fixed-order sums of the 10 fields
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_totals_partial(Geo g, CFields<T> U, double* __restrict__ part)
-{
-    __shared__ double red[NF][NTH / 64];
-    int c = blockIdx.x * NTH + threadIdx.x;
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int f = 0; f < NF; f++) {
-        double v = c < g.n ? (double)U.f[f][c] : 0.0;
-        v = wave_sum(v);
-        if (lane == 0) red[f][wv] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < NF) {
-        double s = 0.0;
-        for (int w = 0; w < NTH / 64; w++) s += red[threadIdx.x][w];
-        part[(size_t)blockIdx.x * NF + threadIdx.x] = s;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_totals_final(const double* __restrict__ part, int nparts,
-                                                       double* __restrict__ out)
-{
-    __shared__ double red[NF][16];
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int f = 0; f < NF; f++) {
-        double s = 0.0;
-        for (int t = threadIdx.x; t < nparts; t += 1024) s += part[(size_t)t * NF + f];
-        s = wave_sum(s);
-        if (lane == 0) red[f][wv] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NF) {
-        double s = 0.0;
-        for (int w = 0; w < 16; w++) s += red[threadIdx.x][w];
-        out[threadIdx.x] = s;
-    }
-}
-
-// primitive (host order rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2) -> conserved
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_init(Geo g, const double* __restrict__ Wp, Fields<T> U, double gamma)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    int i, j, k;
-    decompose(g, c, i, j, k);
-    const size_t N = (size_t)g.n;
-    double rho = Wp[c];
-    double vx = Wp[N + c], vy = Wp[2 * N + c], vz = Wp[3 * N + c];
-    double p = Wp[4 * N + c];
-    double bxf = Wp[5 * N + c], byf = Wp[6 * N + c], bzf = Wp[7 * N + c];
-    double bx = 0.5 * (bxf + Wp[5 * N + nbr<0>(g, c, i, j, k, 1)]);
-    double by = 0.5 * (byf + Wp[6 * N + nbr<1>(g, c, i, j, k, 1)]);
-    double bz = 0.5 * (bzf + Wp[7 * N + nbr<2>(g, c, i, j, k, 1)]);
-    double e = p / (gamma - 1.0);
-    U.f[RHO][c] = (T)rho;
-    U.f[MX][c] = (T)(rho * vx);
-    U.f[MY][c] = (T)(rho * vy);
-    U.f[MZ][c] = (T)(rho * vz);
-    U.f[EI][c] = (T)e;
-    U.f[EN][c] = (T)(e + 0.5 * rho * (vx * vx + vy * vy + vz * vz) + 0.5 * (bx * bx + by * by + bz * bz));
-    U.f[BX][c] = (T)bxf;
-    U.f[BY][c] = (T)byf;
-    U.f[BZ][c] = (T)bzf;
-    U.f[H2][c] = (T)(Wp[8 * N + c] * rho);
-}
-
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_from_f64(Geo g, const double* __restrict__ src, Fields<T> U)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    const size_t N = (size_t)g.n;
-#pragma unroll
-    for (int f = 0; f < NF; f++) U.f[f][c] = (T)src[f * N + c];
-}
-
-template <typename T>
-__global__ __launch_bounds__(NTH) void k_to_f64(Geo g, CFields<T> U, double* __restrict__ dst)
-{
-    int c = blockIdx.x * NTH + threadIdx.x;
-    if (c >= g.n) return;
-    const size_t N = (size_t)g.n;
-#pragma unroll
-    for (int f = 0; f < NF; f++) dst[f * N + c] = (double)U.f[f][c];
-}
-
-__global__ void k_clear_flags(uint32_t* flags)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *flags = 0u;
-}
-
-}  // namespace
-
-// ---------------------------------------------------------------- host runtime
+// ---------------------------------------------------------------- box
 
 struct mhd_box {
     mhd_params p;
@@ -932,7 +42,7 @@ struct mhd_box {
     hipStream_t s;
     int prec;          // MHD_FP64 / MHD_FP32_MIXED
     size_t esz;        // bytes per stored value
-    int nblocks;
+    int nblocks;       // cell-parallel blocks of NTH threads
     char* slot[3];     // three Runge-Kutta copies of the 10 fields
     char* W;           // primitives, 8 x N
     char* F[3];        // per-direction face outputs, 7 x N each
@@ -943,7 +53,7 @@ struct mhd_box {
     int cur[3];        // current slot of the groups H, M, B
     // per-launch event timing (mhd_set_timing)
     int timing;
-    int nev;                    // event pairs recorded in the current step
+    int nev;
     hipEvent_t ev[2 * 64];
     int evcls[64];
     int ev_ready;
@@ -967,27 +77,38 @@ struct Layout {
     size_t slot, W, F, part, misc, total;
 };
 
-bool valid_params(const mhd_params* p)
+bool valid_physics(int32_t precision, double gamma, double cfl, double theta, int32_t chem, double nu, double Tu,
+                   double tu)
 {
-    if (!p) return false;
-    for (int d = 0; d < 3; d++)
-        if (p->n[d] < 1) return false;
-    double n = (double)p->n[0] * p->n[1] * p->n[2];
-    if (n >= 2147483647.0) return false;
-    if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return false;
-    if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return false;
-    if (!(p->theta >= 0.0) || !std::isfinite(p->theta)) return false;
-    if (p->precision != MHD_FP64 && p->precision != MHD_FP32_MIXED) return false;
-    if (p->chemistry != 0 && p->chemistry != 1) return false;
-    if (p->chemistry && !(p->n_unit_cm3 > 0.0 && p->T_unit_K > 0.0 && p->t_unit_s > 0.0)) return false;
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) return false;
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) return false;
+    if (!(theta >= 0.0) || !std::isfinite(theta)) return false;
+    if (precision != MHD_FP64 && precision != MHD_FP32_MIXED) return false;
+    if (chem != 0 && chem != 1) return false;
+    if (chem && !(nu > 0.0 && Tu > 0.0 && tu > 0.0)) return false;
     return true;
 }
 
-Layout layout_of(const mhd_params* p)
+bool valid_dims(const int32_t n[3])
+{
+    for (int d = 0; d < 3; d++)
+        if (n[d] < 1) return false;
+    double c = (double)n[0] * n[1] * n[2];
+    return c < 2147483647.0;
+}
+
+bool valid_params(const mhd_params* p)
+{
+    if (!p || !valid_dims(p->n)) return false;
+    return valid_physics(p->precision, p->gamma, p->cfl, p->theta, p->chemistry, p->n_unit_cm3, p->T_unit_K,
+                         p->t_unit_s);
+}
+
+Layout layout_of(const int32_t n[3], int precision)
 {
     Layout L;
-    size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
-    size_t esz = p->precision == MHD_FP64 ? 8 : 4;
+    size_t N = (size_t)n[0] * n[1] * n[2];
+    size_t esz = precision == MHD_FP64 ? 8 : 4;
     size_t nb = (N + NTH - 1) / NTH;
     L.slot = align256(NF * N * esz);
     L.W = align256(8 * N * esz);
@@ -996,9 +117,46 @@ Layout layout_of(const mhd_params* p)
     size_t stage = align256(10 * N * 8);
     L.F = 3 * fbytes > stage ? 3 * fbytes : stage;
     L.part = align256(nb * NF * sizeof(double));
-    L.misc = 256 + 256 + 256;
+    L.misc = 3 * 256;
     L.total = 3 * L.slot + L.W + L.F + L.part + L.misc;
     return L;
+}
+
+void box_bind(mhd_box* b, const mhd_params* p, const Layout& L)
+{
+    b->p = *p;
+    b->g.nx = p->n[0];
+    b->g.ny = p->n[1];
+    b->g.nz = p->n[2];
+    b->g.nxy = p->n[0] * p->n[1];
+    b->g.n = p->n[0] * p->n[1] * p->n[2];
+    b->s = reinterpret_cast<hipStream_t>(p->stream);
+    b->prec = p->precision;
+    b->esz = p->precision == MHD_FP64 ? 8 : 4;
+    b->nblocks = (b->g.n + NTH - 1) / NTH;
+    char* w = reinterpret_cast<char*>(p->workspace);
+    for (int s = 0; s < 3; s++) {
+        b->slot[s] = w;
+        w += L.slot;
+    }
+    b->W = w;
+    w += L.W;
+    size_t fbytes = align256(NFACE * (size_t)b->g.n * b->esz);
+    for (int d = 0; d < 3; d++) b->F[d] = w + d * fbytes;
+    w += L.F;
+    b->part = reinterpret_cast<double*>(w);
+    w += L.part;
+    b->flags = reinterpret_cast<uint32_t*>(w);
+    b->dt_dev = reinterpret_cast<double*>(w + 256);
+    b->tot_dev = reinterpret_cast<double*>(w + 512);
+    b->cur[0] = b->cur[1] = b->cur[2] = 0;
+    b->timing = 0;
+    b->nev = 0;
+    b->ev_ready = 0;
+    for (int c = 0; c < MHD_NKCLASS; c++) {
+        b->tms[c] = 0.0;
+        b->tcnt[c] = 0;
+    }
 }
 
 template <typename T>
@@ -1051,21 +209,23 @@ const RK rk_coef[3] = { { 0.0, 1.0 }, { 0.75, 0.25 }, { 1.0 / 3.0, 2.0 / 3.0 } }
 
 struct Slots { int h, m, b; };
 
+// ---------------------------------------------------------------- emitters
+
 // event pair around one launch of class cls (no-op unless timing is on)
 struct KTimer {
     mhd_box* b;
     int slot;
     KTimer(mhd_box* box, int cls) : b(box), slot(-1)
     {
-        if (b->timing && b->nev < 64) {
+        if (b && b->timing && b->nev < 64) {
             slot = b->nev++;
             b->evcls[slot] = cls;
-            hipEventRecord(b->ev[2 * slot], b->s);
+            (void)hipEventRecord(b->ev[2 * slot], b->s);
         }
     }
     ~KTimer()
     {
-        if (slot >= 0) hipEventRecord(b->ev[2 * slot + 1], b->s);
+        if (slot >= 0) (void)hipEventRecord(b->ev[2 * slot + 1], b->s);
     }
 };
 
@@ -1083,169 +243,255 @@ int timing_collect(mhd_box* b)
     return MHD_OK;
 }
 
-// x faces: whole rows per block when a row fits one block, else one face per thread
-template <typename T>
-void launch_nonadv_x(mhd_box* b, const T* W, const T* bx, T* F, const StepArgs& a)
+// sends each launch of the program straight to the box's stream
+struct OneEmit {
+    mhd_box* b;
+    template <class Body>
+    void launch(int cls, int blocks, size_t shm, const typename Body::Args& a)
+    {
+        if (blocks <= 0) return;
+        KTimer t(b, cls);
+        if (shm > 65536)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_one<Body>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        k_one<Body><<<blocks, Body::NT, shm, b->s>>>(a);
+    }
+};
+
+// one program position merged over many boxes
+struct MultiRec {
+    void (*go)(const void* tab, const int* bstart, int nbox, int blocks, size_t shm, hipStream_t s);
+    std::vector<char> args;
+    std::vector<int> bstart;
+    int total;
+    size_t shm;
+    size_t off_args, off_bstart;   // offsets in the uploaded table
+};
+
+template <class Body>
+void go_many(const void* tab, const int* bstart, int nbox, int blocks, size_t shm, hipStream_t s)
 {
-    const int nx = b->g.nx;
-    const int maxt = sizeof(T) == 8 ? 512 : 1024;
-    if (nx <= maxt) {
-        int rpb = nx >= 256 ? 1 : 256 / nx;
-        int threads = rpb * nx;
-        int rows = b->g.ny * b->g.nz;
-        int blocks = (rows + rpb - 1) / rpb;
-        size_t shm = (size_t)threads * 18 * sizeof(T);   // at most 72 KiB
-        if (threads <= 256) {
-            k_nonadv_xrows<T, 256><<<blocks, threads, shm, b->s>>>(b->g, W, bx, F, a, rpb);
-        } else if (threads <= 512) {
-            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nonadv_xrows<T, 512>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-            k_nonadv_xrows<T, 512><<<blocks, threads, shm, b->s>>>(b->g, W, bx, F, a, rpb);
-        } else {
-            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nonadv_xrows<T, 1024>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-            k_nonadv_xrows<T, 1024><<<blocks, threads, shm, b->s>>>(b->g, W, bx, F, a, rpb);
+    if (shm > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_many<Body>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    k_many<Body><<<blocks, Body::NT, shm, s>>>(reinterpret_cast<const typename Body::Args*>(tab), bstart, nbox);
+}
+
+struct MultiEmit {
+    std::vector<MultiRec>* recs;
+    size_t k;        // program position within the current box
+    bool first;      // the first box defines the program
+    bool mismatch;
+    template <class Body>
+    void launch(int, int blocks, size_t shm, const typename Body::Args& a)
+    {
+        if (first) {
+            MultiRec r;
+            r.go = &go_many<Body>;
+            r.total = 0;
+            r.shm = 0;
+            r.off_args = r.off_bstart = 0;
+            recs->push_back(r);
         }
+        if (k >= recs->size() || (*recs)[k].go != &go_many<Body>) {
+            mismatch = true;
+            return;
+        }
+        MultiRec& r = (*recs)[k++];
+        const char* p = reinterpret_cast<const char*>(&a);
+        r.args.insert(r.args.end(), p, p + sizeof(a));
+        r.bstart.push_back(r.total);
+        r.total += blocks > 0 ? blocks : 0;
+        r.shm = shm > r.shm ? shm : r.shm;
+    }
+};
+
+// ---------------------------------------------------------------- the step program
+
+template <typename T, class Emit>
+void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, const StepArgs& a)
+{
+    const Geo& g = b->g;
+    T* F0 = reinterpret_cast<T*>(b->F[0]);
+    T* F1 = reinterpret_cast<T*>(b->F[1]);
+    T* F2 = reinterpret_cast<T*>(b->F[2]);
+    FaceArgs<T> fa;
+    fa.g = g;
+    fa.W = W;
+    fa.a = a;
+    // x faces: whole rows per block when a row fits one block, else one face per thread
+    fa.bface = in.f[BX];
+    fa.F = F0;
+    const int maxt = sizeof(T) == 8 ? 512 : 1024;
+    if (g.nx <= maxt) {
+        int rpb = g.nx >= 256 ? 1 : 256 / g.nx;
+        int rows = g.ny * g.nz;
+        fa.rpb = rpb;
+        fa.seg = 0;
+        int blocks = (rows + rpb - 1) / rpb;
+        if (g.nx <= 256)
+            e.template launch<BFaceXRows<T, 256>>(MHD_K_NONADV_FACE, blocks, 256 * 18 * sizeof(T), fa);
+        else if (g.nx <= 512)
+            e.template launch<BFaceXRows<T, 512>>(MHD_K_NONADV_FACE, blocks, 512 * 18 * sizeof(T), fa);
+        else
+            e.template launch<BFaceXRows<T, 1024>>(MHD_K_NONADV_FACE, blocks, 1024 * 18 * sizeof(T), fa);
     } else {
-        k_nonadv_face<T, 0><<<b->nblocks, NTH, 0, b->s>>>(b->g, W, bx, F, a);
+        fa.rpb = 0;
+        fa.seg = 0;
+        e.template launch<BFacePair<T, 0>>(MHD_K_NONADV_FACE, b->nblocks, 0, fa);
+    }
+    // y and z faces: marching segments
+    constexpr int MARCH_SEG = 32;
+    for (int D = 1; D <= 2; D++) {
+        const int nd = D == 1 ? g.ny : g.nz;
+        const int no = D == 1 ? g.nz : g.ny;
+        fa.seg = nd < MARCH_SEG ? nd : MARCH_SEG;
+        fa.rpb = 0;
+        fa.bface = in.f[D == 1 ? BY : BZ];
+        fa.F = D == 1 ? F1 : F2;
+        long long threads = (long long)g.nx * no * ((nd + fa.seg - 1) / fa.seg);
+        int blocks = (int)((threads + NTH - 1) / NTH);
+        if (D == 1)
+            e.template launch<BFaceMarch<T, 1>>(MHD_K_NONADV_FACE, blocks, 0, fa);
+        else
+            e.template launch<BFaceMarch<T, 2>>(MHD_K_NONADV_FACE, blocks, 0, fa);
     }
 }
 
-constexpr int MARCH_SEG = 32;
-
-template <typename T, int D>
-void launch_nonadv_march(mhd_box* b, const T* W, const T* bf, T* F, const StepArgs& a)
+template <typename T, class Emit>
+void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg,
+                          bool first)
 {
-    const int nd = D == 1 ? b->g.ny : b->g.nz;
-    const int no = D == 1 ? b->g.nz : b->g.ny;
-    int seg = nd < MARCH_SEG ? nd : MARCH_SEG;
-    long long threads = (long long)b->g.nx * no * ((nd + seg - 1) / seg);
-    int blocks = (int)((threads + NTH - 1) / NTH);
-    k_nonadv_march<T, D><<<blocks, NTH, 0, b->s>>>(b->g, W, bf, F, a, seg);
-}
-
-template <typename T>
-int nonadv_substage(mhd_box* b, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg, bool first)
-{
-    dim3 grid(b->nblocks), blk(NTH);
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
     T* W = reinterpret_cast<T*>(b->W);
-    T* F0 = reinterpret_cast<T*>(b->F[0]);
-    T* F1 = reinterpret_cast<T*>(b->F[1]);
-    T* F2 = reinterpret_cast<T*>(b->F[2]);
-    {
-        KTimer t(b, MHD_K_PRIM);
-        k_prim<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), W, a, b->flags, first ? b->dt_dev : nullptr);
-    }
-    {
-        KTimer t(b, MHD_K_NONADV_FACE);
-        launch_nonadv_x<T>(b, W, in.f[BX], F0, a);
-    }
-    {
-        KTimer t(b, MHD_K_NONADV_FACE);
-        launch_nonadv_march<T, 1>(b, W, in.f[BY], F1, a);
-    }
-    {
-        KTimer t(b, MHD_K_NONADV_FACE);
-        launch_nonadv_march<T, 2>(b, W, in.f[BZ], F2, a);
-    }
-    {
-        KTimer t(b, MHD_K_NONADV_UPDATE);
-        k_nonadv_update<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), cview(S), out, F0, F1, F2, a, rk, dbg);
-    }
-    return launch_status();
+    typename BPrim<T>::Args pa;
+    pa.g = b->g;
+    pa.U = cview(in);
+    pa.W = W;
+    pa.a = a;
+    pa.flags = b->flags;
+    pa.dt_cfl = first ? b->dt_dev : nullptr;
+    e.template launch<BPrim<T>>(MHD_K_PRIM, b->nblocks, 0, pa);
+    emit_nonadv_faces<T>(b, e, W, in, a);
+    typename BNonadvUpdate<T>::Args ua;
+    ua.g = b->g;
+    ua.U = cview(in);
+    ua.S = cview(S);
+    ua.O = out;
+    ua.Fx = reinterpret_cast<T*>(b->F[0]);
+    ua.Fy = reinterpret_cast<T*>(b->F[1]);
+    ua.Fz = reinterpret_cast<T*>(b->F[2]);
+    ua.a = a;
+    ua.rk = rk;
+    ua.dbg = dbg;
+    e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, b->nblocks, 0, ua);
 }
 
-template <typename T>
-int adv_substage(mhd_box* b, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg)
+template <typename T, int D, class Emit>
+void emit_adv_face(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a)
 {
-    dim3 grid(b->nblocks), blk(NTH);
+    typename BAdvFace<T, D>::Args fa;
+    fa.g = b->g;
+    fa.U = cview(in);
+    fa.a = a;
+    fa.F = reinterpret_cast<T*>(b->F[D]);
+    e.template launch<BAdvFace<T, D>>(MHD_K_ADV_FACE, b->nblocks, 0, fa);
+}
+
+template <typename T, class Emit>
+void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg)
+{
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
-    T* F0 = reinterpret_cast<T*>(b->F[0]);
-    T* F1 = reinterpret_cast<T*>(b->F[1]);
-    T* F2 = reinterpret_cast<T*>(b->F[2]);
-    {
-        KTimer t(b, MHD_K_ADV_FACE);
-        k_adv_face<T, 0><<<grid, blk, 0, b->s>>>(b->g, cview(in), F0, a);
-    }
-    {
-        KTimer t(b, MHD_K_ADV_FACE);
-        k_adv_face<T, 1><<<grid, blk, 0, b->s>>>(b->g, cview(in), F1, a);
-    }
-    {
-        KTimer t(b, MHD_K_ADV_FACE);
-        k_adv_face<T, 2><<<grid, blk, 0, b->s>>>(b->g, cview(in), F2, a);
-    }
-    {
-        KTimer t(b, MHD_K_ADV_UPDATE);
-        k_adv_update<T><<<grid, blk, 0, b->s>>>(b->g, cview(in), cview(S), out, F0, F1, F2, a, rk, dbg);
-    }
-    return launch_status();
+    emit_adv_face<T, 0>(b, e, in, a);
+    emit_adv_face<T, 1>(b, e, in, a);
+    emit_adv_face<T, 2>(b, e, in, a);
+    typename BAdvUpdate<T>::Args ua;
+    ua.g = b->g;
+    ua.U = cview(in);
+    ua.S = cview(S);
+    ua.O = out;
+    ua.Fx = reinterpret_cast<T*>(b->F[0]);
+    ua.Fy = reinterpret_cast<T*>(b->F[1]);
+    ua.Fz = reinterpret_cast<T*>(b->F[2]);
+    ua.a = a;
+    ua.rk = rk;
+    ua.dbg = dbg;
+    e.template launch<BAdvUpdate<T>>(MHD_K_ADV_UPDATE, b->nblocks, 0, ua);
 }
 
 // NONADV stage: the M and B groups each rotate through their three slots
 // (stage start S, then A, B, A); H is read from its current slot.
-template <typename T>
-int nonadv_stage(mhd_box* b, const StepArgs& a, bool first)
+template <typename T, class Emit>
+void emit_nonadv_stage(mhd_box* b, Emit& e, const StepArgs& a, bool first)
 {
     int h = b->cur[GH], Sm = b->cur[GM], Sb = b->cur[GB];
     Slots S0 = { h, Sm, Sb };
     Slots A = { h, (Sm + 1) % 3, (Sb + 1) % 3 };
     Slots B2 = { h, (Sm + 2) % 3, (Sb + 2) % 3 };
-    int st;
-    if ((st = nonadv_substage<T>(b, S0, S0, A, a, rk_coef[0], 0, first))) return st;
-    if ((st = nonadv_substage<T>(b, A, S0, B2, a, rk_coef[1], 0, false))) return st;
-    if ((st = nonadv_substage<T>(b, B2, S0, A, a, rk_coef[2], 0, false))) return st;
+    emit_nonadv_substage<T>(b, e, S0, S0, A, a, rk_coef[0], 0, first);
+    emit_nonadv_substage<T>(b, e, A, S0, B2, a, rk_coef[1], 0, false);
+    emit_nonadv_substage<T>(b, e, B2, S0, A, a, rk_coef[2], 0, false);
     b->cur[GM] = A.m;
     b->cur[GB] = A.b;
-    return MHD_OK;
 }
 
 // ADV stage: the H and M groups rotate; B is read from its current slot
-template <typename T>
-int adv_stage(mhd_box* b, const StepArgs& a)
+template <typename T, class Emit>
+void emit_adv_stage(mhd_box* b, Emit& e, const StepArgs& a)
 {
     int Sh = b->cur[GH], Sm = b->cur[GM], bb = b->cur[GB];
     Slots S0 = { Sh, Sm, bb };
     Slots A = { (Sh + 1) % 3, (Sm + 1) % 3, bb };
     Slots B2 = { (Sh + 2) % 3, (Sm + 2) % 3, bb };
-    int st;
-    if ((st = adv_substage<T>(b, S0, S0, A, a, rk_coef[0], 0))) return st;
-    if ((st = adv_substage<T>(b, A, S0, B2, a, rk_coef[1], 0))) return st;
-    if ((st = adv_substage<T>(b, B2, S0, A, a, rk_coef[2], 0))) return st;
+    emit_adv_substage<T>(b, e, S0, S0, A, a, rk_coef[0], 0);
+    emit_adv_substage<T>(b, e, A, S0, B2, a, rk_coef[1], 0);
+    emit_adv_substage<T>(b, e, B2, S0, A, a, rk_coef[2], 0);
     b->cur[GH] = A.h;
     b->cur[GM] = A.m;
-    return MHD_OK;
 }
 
-template <typename T>
-int tail(mhd_box* b, const StepArgs& a, int mode)
+template <typename T, class Emit>
+void emit_tail(mhd_box* b, Emit& e, const StepArgs& a, int mode)
 {
-    Fields<T> u = view<T>(b, b->cur[GH], b->cur[GM], b->cur[GB]);
-    {
-        KTimer t(b, MHD_K_TAIL);
-        k_tail<T><<<b->nblocks, NTH, 0, b->s>>>(b->g, u, a, chem_args(b), mode, b->part, b->flags);
-    }
-    double cflh = b->p.cfl * (1.0 / (double)b->p.n[0]);
-    {
-        KTimer t(b, MHD_K_REDUCE);
-        k_reduce_dt<<<1, 1024, 0, b->s>>>(b->part, b->nblocks, cflh, b->dt_dev);
-    }
-    return launch_status();
+    typename BTail<T>::Args ta;
+    ta.g = b->g;
+    ta.U = view<T>(b, b->cur[GH], b->cur[GM], b->cur[GB]);
+    ta.a = a;
+    ta.ch = chem_args(b);
+    ta.mode = mode;
+    ta.part = b->part;
+    ta.flags = b->flags;
+    e.template launch<BTail<T>>(MHD_K_TAIL, b->nblocks, 0, ta);
+    BReduceDt::Args ra;
+    ra.part = b->part;
+    ra.nparts = b->nblocks;
+    ra.cflh = b->p.cfl * (1.0 / (double)b->p.n[0]);
+    ra.dt = b->dt_dev;
+    e.template launch<BReduceDt>(MHD_K_REDUCE, 1, 0, ra);
 }
+
+template <typename T, class Emit>
+void emit_step(mhd_box* b, Emit& e, const StepArgs& a)
+{
+    emit_nonadv_stage<T>(b, e, a, true);
+    emit_adv_stage<T>(b, e, a);
+    emit_tail<T>(b, e, a, 1);
+}
+
+// ---------------------------------------------------------------- single-box operations
 
 template <typename T>
 int full_step(mhd_box* b, double dt, bool dev)
 {
     StepArgs a = step_args(b, dt, dev);
-    int st;
-    if ((st = nonadv_stage<T>(b, a, true))) return st;
-    if ((st = adv_stage<T>(b, a))) return st;
-    if ((st = tail<T>(b, a, 1))) return st;
+    OneEmit e{ b };
+    emit_step<T>(b, e, a);
+    int st = launch_status();
+    if (st) return st;
     return timing_collect(b);
 }
 
@@ -1269,13 +515,30 @@ int load_f64(mhd_box* b, const double* host, bool prim)
         return MHD_EDEVICE;
     b->cur[GH] = b->cur[GM] = b->cur[GB] = 0;
     Fields<T> u = view<T>(b, 0, 0, 0);
-    if (prim)
-        k_init<T><<<b->nblocks, NTH, 0, b->s>>>(b->g, stage, u, b->p.gamma);
-    else
-        k_from_f64<T><<<b->nblocks, NTH, 0, b->s>>>(b->g, stage, u);
-    k_clear_flags<<<1, 64, 0, b->s>>>(b->flags);
+    int saved = b->timing;
+    b->timing = 0;
+    OneEmit e{ b };
+    if (prim) {
+        typename BInit<T>::Args ia;
+        ia.g = b->g;
+        ia.Wp = stage;
+        ia.U = u;
+        ia.gamma = b->p.gamma;
+        e.template launch<BInit<T>>(0, b->nblocks, 0, ia);
+    } else {
+        typename BFromF64<T>::Args ia;
+        ia.g = b->g;
+        ia.src = stage;
+        ia.U = u;
+        e.template launch<BFromF64<T>>(0, b->nblocks, 0, ia);
+    }
+    BClearFlags::Args ca;
+    ca.flags = b->flags;
+    e.template launch<BClearFlags>(0, 1, 0, ca);
     StepArgs a = step_args(b, 0.0, false);
-    int st = tail<T>(b, a, 0);
+    emit_tail<T>(b, e, a, 0);
+    b->timing = saved;
+    int st = launch_status();
     if (st) return st;
     if (hipStreamSynchronize(b->s) != hipSuccess) return MHD_EDEVICE;
     return MHD_OK;
@@ -1286,8 +549,11 @@ int get_f64(mhd_box* b, double* host)
 {
     size_t N = (size_t)b->g.n;
     double* stage = reinterpret_cast<double*>(b->F[0]);
-    Fields<T> u = view<T>(b, b->cur[GH], b->cur[GM], b->cur[GB]);
-    k_to_f64<T><<<b->nblocks, NTH, 0, b->s>>>(b->g, cview(u), stage);
+    typename BToF64<T>::Args ta;
+    ta.g = b->g;
+    ta.U = cview(view<T>(b, b->cur[GH], b->cur[GM], b->cur[GB]));
+    ta.dst = stage;
+    k_one<BToF64<T>><<<b->nblocks, NTH, 0, b->s>>>(ta);
     if (launch_status()) return MHD_EDEVICE;
     if (hipMemcpyAsync(host, stage, NF * N * sizeof(double), hipMemcpyDeviceToHost, b->s) != hipSuccess)
         return MHD_EDEVICE;
@@ -1295,12 +561,25 @@ int get_f64(mhd_box* b, double* host)
 }
 
 template <typename T>
+int totals_launch(mhd_box* b)
+{
+    typename BTotalsPartial<T>::Args pa;
+    pa.g = b->g;
+    pa.U = cview(view<T>(b, b->cur[GH], b->cur[GM], b->cur[GB]));
+    pa.part = b->part;
+    k_one<BTotalsPartial<T>><<<b->nblocks, NTH, 0, b->s>>>(pa);
+    BTotalsFinal::Args fa;
+    fa.part = b->part;
+    fa.nparts = b->nblocks;
+    fa.out = b->tot_dev;
+    k_one<BTotalsFinal><<<1, BTotalsFinal::NT, 0, b->s>>>(fa);
+    return launch_status();
+}
+
+template <typename T>
 int totals(mhd_box* b, double* out)
 {
-    Fields<T> u = view<T>(b, b->cur[GH], b->cur[GM], b->cur[GB]);
-    k_totals_partial<T><<<b->nblocks, NTH, 0, b->s>>>(b->g, cview(u), b->part);
-    k_totals_final<<<1, 1024, 0, b->s>>>(b->part, b->nblocks, b->tot_dev);
-    if (launch_status()) return MHD_EDEVICE;
+    if (totals_launch<T>(b)) return MHD_EDEVICE;
     if (hipMemcpyAsync(out, b->tot_dev, NF * sizeof(double), hipMemcpyDeviceToHost, b->s) != hipSuccess)
         return MHD_EDEVICE;
     return sync_and_flags(b);
@@ -1310,10 +589,11 @@ template <typename T>
 int debug_stage(mhd_box* b, int stage, double dt)
 {
     StepArgs a = step_args(b, dt, false);
+    OneEmit e{ b };
     switch (stage) {
-    case MHD_STAGE_NONADV: return nonadv_stage<T>(b, a, false);
-    case MHD_STAGE_ADV: return adv_stage<T>(b, a);
-    case MHD_STAGE_TAIL: return tail<T>(b, a, 1);
+    case MHD_STAGE_NONADV: emit_nonadv_stage<T>(b, e, a, false); break;
+    case MHD_STAGE_ADV: emit_adv_stage<T>(b, e, a); break;
+    case MHD_STAGE_TAIL: emit_tail<T>(b, e, a, 1); break;
     case MHD_STAGE_NONADV_RHS:
     case MHD_STAGE_ADV_RHS: {
         // tau R(U) of one substage into all ten fields of a free slot; needs
@@ -1322,14 +602,236 @@ int debug_stage(mhd_box* b, int stage, double dt)
         if (b->cur[GH] != S || b->cur[GB] != S) return MHD_EINVAL;
         int O = (S + 1) % 3;
         Slots s0 = { S, S, S }, so = { O, O, O };
-        int st = stage == MHD_STAGE_NONADV_RHS ? nonadv_substage<T>(b, s0, s0, so, a, rk_coef[0], 1, false)
-                                               : adv_substage<T>(b, s0, s0, so, a, rk_coef[0], 1);
-        if (st) return st;
+        if (stage == MHD_STAGE_NONADV_RHS)
+            emit_nonadv_substage<T>(b, e, s0, s0, so, a, rk_coef[0], 1, false);
+        else
+            emit_adv_substage<T>(b, e, s0, s0, so, a, rk_coef[0], 1);
         b->cur[GH] = b->cur[GM] = b->cur[GB] = O;
-        return MHD_OK;
+        break;
     }
     default: return MHD_EINVAL;
     }
+    return launch_status();
+}
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- server
+
+struct mhd_server {
+    mhd_server_params p;
+    hipStream_t s;
+    char* dtab;                // device launch tables (start of the workspace)
+    char* htab;                // pinned host copy of the tables
+    char* pool;                // the rest of the workspace: box allocations
+    size_t pool_bytes;
+    std::vector<std::pair<size_t, size_t>> freel;   // (offset, size), sorted by offset
+    size_t used, peak;
+    struct Pending {
+        uint64_t id;
+        mhd_request r;
+        std::vector<double> prim;
+        double t_submit;
+    };
+    struct Active {
+        uint64_t id;
+        mhd_box* box;
+        size_t off, bytes;
+        int steps, done, keep;
+        double t_submit, t_admit;
+    };
+    std::deque<Pending> pending;
+    std::vector<Active> active;
+    std::deque<mhd_completion> done;
+    std::unordered_map<uint64_t, std::vector<double>> results;
+    uint64_t next_id;
+    double t0;
+    std::vector<MultiRec> recs;
+};
+
+namespace {
+
+constexpr size_t SERVER_TAB_BYTES = (size_t)32 << 20;
+constexpr int SERVER_MAX_SLOTS = 1024;
+constexpr int SERVER_MAX_NX = 256;
+
+bool pool_alloc(mhd_server* sv, size_t bytes, size_t* off)
+{
+    bytes = align256(bytes);
+    for (size_t i = 0; i < sv->freel.size(); i++) {
+        if (sv->freel[i].second >= bytes) {
+            *off = sv->freel[i].first;
+            sv->freel[i].first += bytes;
+            sv->freel[i].second -= bytes;
+            if (sv->freel[i].second == 0) sv->freel.erase(sv->freel.begin() + i);
+            sv->used += bytes;
+            if (sv->used > sv->peak) sv->peak = sv->used;
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(mhd_server* sv, size_t off, size_t bytes)
+{
+    bytes = align256(bytes);
+    sv->used -= bytes;
+    size_t i = 0;
+    while (i < sv->freel.size() && sv->freel[i].first < off) i++;
+    sv->freel.insert(sv->freel.begin() + i, std::make_pair(off, bytes));
+    if (i + 1 < sv->freel.size() && sv->freel[i].first + sv->freel[i].second == sv->freel[i + 1].first) {
+        sv->freel[i].second += sv->freel[i + 1].second;
+        sv->freel.erase(sv->freel.begin() + i + 1);
+    }
+    if (i > 0 && sv->freel[i - 1].first + sv->freel[i - 1].second == sv->freel[i].first) {
+        sv->freel[i - 1].second += sv->freel[i].second;
+        sv->freel.erase(sv->freel.begin() + i);
+    }
+}
+
+mhd_params box_params(const mhd_server* sv, const int32_t n[3], void* ws, size_t bytes)
+{
+    mhd_params bp;
+    bp.n[0] = n[0];
+    bp.n[1] = n[1];
+    bp.n[2] = n[2];
+    bp.gamma = sv->p.gamma;
+    bp.cfl = sv->p.cfl;
+    bp.precision = sv->p.precision;
+    bp.theta = sv->p.theta;
+    bp.chemistry = sv->p.chemistry;
+    bp.n_unit_cm3 = sv->p.n_unit_cm3;
+    bp.T_unit_K = sv->p.T_unit_K;
+    bp.t_unit_s = sv->p.t_unit_s;
+    bp.stream = sv->p.stream;
+    bp.workspace = ws;
+    bp.workspace_bytes = bytes;
+    return bp;
+}
+
+int server_admit(mhd_server* sv)
+{
+    while (!sv->pending.empty() && (int)sv->active.size() < sv->p.max_slots) {
+        mhd_server::Pending& q = sv->pending.front();
+        Layout L = layout_of(q.r.n, sv->p.precision);
+        size_t off;
+        if (!pool_alloc(sv, L.total, &off)) break;   // first come, first served: wait for memory
+        mhd_box* b = new (std::nothrow) mhd_box;
+        if (!b) {
+            pool_free(sv, off, L.total);
+            return MHD_ENOMEM;
+        }
+        mhd_params bp = box_params(sv, q.r.n, sv->pool + off, L.total);
+        box_bind(b, &bp, L);
+        int st = sv->p.precision == MHD_FP64 ? load_f64<double>(b, q.prim.data(), true)
+                                             : load_f64<float>(b, q.prim.data(), true);
+        if (st) {
+            delete b;
+            pool_free(sv, off, L.total);
+            return st;
+        }
+        mhd_server::Active a;
+        a.id = q.id;
+        a.box = b;
+        a.off = off;
+        a.bytes = L.total;
+        a.steps = q.r.steps;
+        a.done = 0;
+        a.keep = q.r.keep_state;
+        a.t_submit = q.t_submit;
+        a.t_admit = now_s() - sv->t0;
+        sv->active.push_back(a);
+        sv->pending.pop_front();
+    }
+    return MHD_OK;
+}
+
+// one step of every active box, merged into one launch per program position
+template <typename T>
+int server_step(mhd_server* sv)
+{
+    sv->recs.clear();
+    MultiEmit e{ &sv->recs, 0, true, false };
+    for (size_t i = 0; i < sv->active.size(); i++) {
+        mhd_box* b = sv->active[i].box;
+        e.k = 0;
+        e.first = i == 0;
+        StepArgs a = step_args(b, 0.0, true);
+        emit_step<T>(b, e, a);
+        if (e.mismatch || e.k != sv->recs.size()) return MHD_EINVAL;
+    }
+    // pack the tables and upload them once
+    size_t off = 0;
+    for (MultiRec& r : sv->recs) {
+        off = align256(off);
+        r.off_args = off;
+        off += r.args.size();
+        off = align256(off);
+        r.off_bstart = off;
+        off += r.bstart.size() * sizeof(int);
+    }
+    if (off > SERVER_TAB_BYTES) return MHD_ENOMEM;
+    for (MultiRec& r : sv->recs) {
+        memcpy(sv->htab + r.off_args, r.args.data(), r.args.size());
+        memcpy(sv->htab + r.off_bstart, r.bstart.data(), r.bstart.size() * sizeof(int));
+    }
+    if (hipMemcpyAsync(sv->dtab, sv->htab, off, hipMemcpyHostToDevice, sv->s) != hipSuccess) return MHD_EDEVICE;
+    int nbox = (int)sv->active.size();
+    for (MultiRec& r : sv->recs) {
+        if (r.total == 0) continue;
+        r.go(sv->dtab + r.off_args, reinterpret_cast<const int*>(sv->dtab + r.off_bstart), nbox, r.total, r.shm,
+             sv->s);
+    }
+    return launch_status();
+}
+
+int server_progress(mhd_server* sv, int* nact, int* npend)
+{
+    int st = server_admit(sv);
+    if (st) return st;
+    if (!sv->active.empty()) {
+        st = sv->p.precision == MHD_FP64 ? server_step<double>(sv) : server_step<float>(sv);
+        if (st) return st;
+        if (hipStreamSynchronize(sv->s) != hipSuccess) return MHD_EDEVICE;
+        std::vector<mhd_server::Active> keep;
+        for (mhd_server::Active& a : sv->active) {
+            a.done++;
+            if (a.done < a.steps) {
+                keep.push_back(a);
+                continue;
+            }
+            mhd_completion c;
+            memset(&c, 0, sizeof(c));
+            c.id = a.id;
+            c.steps = a.done;
+            c.t_submit = a.t_submit;
+            c.t_admit = a.t_admit;
+            c.cells = (int64_t)a.box->g.n;
+            c.bytes = a.bytes;
+            int s2 = sv->p.precision == MHD_FP64 ? totals<double>(a.box, c.totals) : totals<float>(a.box, c.totals);
+            c.status = s2;
+            if (a.keep && (s2 == MHD_OK || s2 == MHD_ENONPHYS || s2 == MHD_ECFL)) {
+                std::vector<double> buf((size_t)NF * a.box->g.n);
+                int s3 = sv->p.precision == MHD_FP64 ? get_f64<double>(a.box, buf.data())
+                                                     : get_f64<float>(a.box, buf.data());
+                if (s3 == MHD_OK || s3 == s2) sv->results[a.id].swap(buf);
+            }
+            c.t_done = now_s() - sv->t0;
+            sv->done.push_back(c);
+            pool_free(sv, a.off, a.bytes);
+            delete a.box;
+        }
+        sv->active.swap(keep);
+    }
+    if (nact) *nact = (int)sv->active.size();
+    if (npend) *npend = (int)sv->pending.size();
+    return MHD_OK;
 }
 
 }  // namespace
@@ -1341,7 +843,7 @@ extern "C" {
 size_t mhd_workspace_bytes(const mhd_params* p)
 {
     if (!valid_params(p)) return 0;
-    return layout_of(p).total;
+    return layout_of(p->n, p->precision).total;
 }
 
 int mhd_create(const mhd_params* p, mhd_box** out)
@@ -1349,44 +851,12 @@ int mhd_create(const mhd_params* p, mhd_box** out)
     if (!out) return MHD_EINVAL;
     *out = nullptr;
     if (!valid_params(p)) return MHD_EINVAL;
-    Layout L = layout_of(p);
+    Layout L = layout_of(p->n, p->precision);
     if (!p->workspace || p->workspace_bytes < L.total) return MHD_ENOMEM;
     if (((uintptr_t)p->workspace) & 255) return MHD_EINVAL;
     mhd_box* b = new (std::nothrow) mhd_box;
     if (!b) return MHD_ENOMEM;
-    b->p = *p;
-    b->g.nx = p->n[0];
-    b->g.ny = p->n[1];
-    b->g.nz = p->n[2];
-    b->g.nxy = p->n[0] * p->n[1];
-    b->g.n = p->n[0] * p->n[1] * p->n[2];
-    b->s = reinterpret_cast<hipStream_t>(p->stream);
-    b->prec = p->precision;
-    b->esz = p->precision == MHD_FP64 ? 8 : 4;
-    b->nblocks = (b->g.n + NTH - 1) / NTH;
-    char* w = reinterpret_cast<char*>(p->workspace);
-    for (int s = 0; s < 3; s++) {
-        b->slot[s] = w;
-        w += L.slot;
-    }
-    b->W = w;
-    w += L.W;
-    size_t fbytes = align256(NFACE * (size_t)b->g.n * b->esz);
-    for (int d = 0; d < 3; d++) b->F[d] = w + d * fbytes;
-    w += L.F;
-    b->part = reinterpret_cast<double*>(w);
-    w += L.part;
-    b->flags = reinterpret_cast<uint32_t*>(w);
-    b->dt_dev = reinterpret_cast<double*>(w + 256);
-    b->tot_dev = reinterpret_cast<double*>(w + 512);
-    b->cur[0] = b->cur[1] = b->cur[2] = 0;
-    b->timing = 0;
-    b->nev = 0;
-    b->ev_ready = 0;
-    for (int c = 0; c < MHD_NKCLASS; c++) {
-        b->tms[c] = 0.0;
-        b->tcnt[c] = 0;
-    }
+    box_bind(b, p, L);
     *out = b;
     return MHD_OK;
 }
@@ -1475,7 +945,7 @@ int mhd_debug_stage(mhd_box* b, int stage, double dt)
 int mhd_destroy(mhd_box* b)
 {
     if (b && b->ev_ready)
-        for (int i = 0; i < 2 * 64; i++) hipEventDestroy(b->ev[i]);
+        for (int i = 0; i < 2 * 64; i++) (void)hipEventDestroy(b->ev[i]);
     delete b;
     return MHD_OK;
 }
@@ -1491,6 +961,111 @@ const char* mhd_strerror(int status)
     case MHD_ENONPHYS: return "non-finite or non-positive density or internal energy";
     default: return "unknown status";
     }
+}
+
+size_t mhd_server_reserved_bytes(void) { return SERVER_TAB_BYTES; }
+
+size_t mhd_server_box_bytes(const mhd_server_params* p, const int32_t n[3])
+{
+    if (!p || !n || !valid_dims(n)) return 0;
+    if (p->precision != MHD_FP64 && p->precision != MHD_FP32_MIXED) return 0;
+    return align256(layout_of(n, p->precision).total);
+}
+
+int mhd_server_create(const mhd_server_params* p, mhd_server** out)
+{
+    if (!out) return MHD_EINVAL;
+    *out = nullptr;
+    if (!p) return MHD_EINVAL;
+    if (!valid_physics(p->precision, p->gamma, p->cfl, p->theta, p->chemistry, p->n_unit_cm3, p->T_unit_K,
+                       p->t_unit_s))
+        return MHD_EINVAL;
+    if (p->max_slots < 1 || p->max_slots > SERVER_MAX_SLOTS) return MHD_EINVAL;
+    if (!p->workspace || p->workspace_bytes < SERVER_TAB_BYTES + 4096) return MHD_ENOMEM;
+    if (((uintptr_t)p->workspace) & 255) return MHD_EINVAL;
+    mhd_server* sv = new (std::nothrow) mhd_server;
+    if (!sv) return MHD_ENOMEM;
+    sv->p = *p;
+    sv->s = reinterpret_cast<hipStream_t>(p->stream);
+    sv->dtab = reinterpret_cast<char*>(p->workspace);
+    sv->pool = sv->dtab + SERVER_TAB_BYTES;
+    sv->pool_bytes = (p->workspace_bytes - SERVER_TAB_BYTES) & ~(size_t)255;
+    sv->freel.push_back(std::make_pair((size_t)0, sv->pool_bytes));
+    sv->used = sv->peak = 0;
+    sv->next_id = 1;
+    sv->t0 = now_s();
+    sv->htab = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&sv->htab), SERVER_TAB_BYTES, hipHostMallocDefault) != hipSuccess) {
+        delete sv;
+        return MHD_EDEVICE;
+    }
+    *out = sv;
+    return MHD_OK;
+}
+
+int mhd_server_submit(mhd_server* sv, const mhd_request* r, const double* prim, uint64_t* id)
+{
+    if (!sv || !r || !prim || !id) return MHD_EINVAL;
+    if (!valid_dims(r->n) || r->steps < 1) return MHD_EINVAL;
+    if (r->n[0] > SERVER_MAX_NX) return MHD_EINVAL;
+    if (align256(layout_of(r->n, sv->p.precision).total) > sv->pool_bytes) return MHD_ENOMEM;
+    mhd_server::Pending q;
+    q.id = sv->next_id++;
+    q.r = *r;
+    size_t n = (size_t)r->n[0] * r->n[1] * r->n[2];
+    q.prim.assign(prim, prim + 9 * n);
+    q.t_submit = now_s() - sv->t0;
+    sv->pending.push_back(std::move(q));
+    *id = sv->pending.back().id;
+    return MHD_OK;
+}
+
+int mhd_server_progress(mhd_server* sv, int* n_active, int* n_pending)
+{
+    if (!sv) return MHD_EINVAL;
+    return server_progress(sv, n_active, n_pending);
+}
+
+int mhd_server_poll(mhd_server* sv, mhd_completion* out, int cap, int* n)
+{
+    if (!sv || !n || (cap > 0 && !out)) return MHD_EINVAL;
+    int k = 0;
+    while (k < cap && !sv->done.empty()) {
+        out[k++] = sv->done.front();
+        sv->done.pop_front();
+    }
+    *n = k;
+    return MHD_OK;
+}
+
+int mhd_server_result(mhd_server* sv, uint64_t id, double* cons_out, size_t count)
+{
+    if (!sv || !cons_out) return MHD_EINVAL;
+    auto it = sv->results.find(id);
+    if (it == sv->results.end()) return MHD_EINVAL;
+    if (count != it->second.size()) return MHD_EINVAL;
+    memcpy(cons_out, it->second.data(), count * sizeof(double));
+    sv->results.erase(it);
+    return MHD_OK;
+}
+
+int mhd_server_memory(mhd_server* sv, size_t* used, size_t* peak, size_t* capacity)
+{
+    if (!sv) return MHD_EINVAL;
+    if (used) *used = sv->used;
+    if (peak) *peak = sv->peak;
+    if (capacity) *capacity = sv->pool_bytes;
+    return MHD_OK;
+}
+
+int mhd_server_destroy(mhd_server* sv)
+{
+    if (!sv) return MHD_OK;
+    (void)hipStreamSynchronize(sv->s);
+    for (mhd_server::Active& a : sv->active) delete a.box;
+    if (sv->htab) (void)hipHostFree(sv->htab);
+    delete sv;
+    return MHD_OK;
 }
 
 }  // extern "C"

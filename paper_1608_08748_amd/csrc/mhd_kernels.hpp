@@ -1,0 +1,696 @@
+// Kernels of the step.  Every kernel is a Body with an argument struct and a
+// run(args, local block, thread) function; k_one launches it for one box,
+// k_many for many boxes at once (the block -> box map is a prefix table of
+// per-box block counts), so a box computes bit for bit the same alone or
+// batched with others.  Included by mhd.hip only.
+#pragma once
+
+#include "mhd_math.hpp"
+
+namespace mhd {
+
+struct StepArgs {
+    double dt_val;          // explicit step, or
+    const double* dt_dev;   // device-resident CFL step when non-null
+    double gamma;
+    double h;               // 1 / nx
+    double theta;
+    double cfl_tol;         // relative slack of the dt <= CFL-bound check
+};
+
+__device__ __forceinline__ double step_dt(const StepArgs& a)
+{
+    return a.dt_dev ? *a.dt_dev : a.dt_val;
+}
+
+struct RK { double a, b; };
+
+struct ChemArgs;
+
+// ---------------------------------------------------------------- launch wrappers
+
+template <class Body>
+__global__ __launch_bounds__(Body::NT) void k_one(typename Body::Args a)
+{
+    Body::run(a, (int)blockIdx.x, (int)threadIdx.x);
+}
+
+template <class Body>
+__global__ __launch_bounds__(Body::NT) void k_many(const typename Body::Args* __restrict__ tab,
+                                                   const int* __restrict__ bstart, int nbox)
+{
+    int blk = (int)blockIdx.x;
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bstart[mid] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    Body::run(tab[lo], blk - bstart[lo], (int)threadIdx.x);
+}
+
+// ---------------------------------------------------------------- NONADV
+
+// primitive state of every cell: rho, vx, vy, vz, Bcx, Bcy, Bcz, p
+template <typename T>
+struct BPrim {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        CFields<T> U;
+        T* W;
+        StepArgs a;
+        uint32_t* flags;
+        const double* dt_cfl;   // non-null: check the explicit dt against it
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        int c = blk * NT + tid;
+        if (c == 0 && A.dt_cfl && !A.a.dt_dev) {
+            if (A.a.dt_val > *A.dt_cfl * (1.0 + A.a.cfl_tol)) atomicOr(A.flags, 2u);
+        }
+        if (c >= g.n) return;
+        int i, j, k;
+        decompose(g, c, i, j, k);
+        const size_t N = (size_t)g.n;
+        T* W = A.W;
+        T rho = A.U.f[RHO][c];
+        W[0 * N + c] = rho;
+        W[1 * N + c] = A.U.f[MX][c] / rho;
+        W[2 * N + c] = A.U.f[MY][c] / rho;
+        W[3 * N + c] = A.U.f[MZ][c] / rho;
+        W[4 * N + c] = T(0.5) * (A.U.f[BX][c] + A.U.f[BX][nbr<0>(g, c, i, j, k, 1)]);
+        W[5 * N + c] = T(0.5) * (A.U.f[BY][c] + A.U.f[BY][nbr<1>(g, c, i, j, k, 1)]);
+        W[6 * N + c] = T(0.5) * (A.U.f[BZ][c] + A.U.f[BZ][nbr<2>(g, c, i, j, k, 1)]);
+        W[7 * N + c] = T(A.a.gamma - 1.0) * A.U.f[EI][c];
+    }
+};
+
+// primitive-array slots of the six parabola variables for faces along D:
+// (vn, vt1, vt2, Bt1, Bt2, p) in the W layout rho, vx, vy, vz, Bcx, Bcy, Bcz, p
+template <int D> struct Vars {
+    static constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    static constexpr int f[6] = { 1 + D, 1 + T1, 1 + T2, 4 + T1, 4 + T2, 7 };
+};
+
+template <typename T>
+__device__ __forceinline__ void store_face(T* __restrict__ F, size_t N, int c, const T out[7])
+{
+#pragma unroll
+    for (int q = 0; q < 7; q++) F[q * N + c] = out[q];
+}
+
+template <typename T>
+struct FaceArgs {
+    Geo g;
+    const T* W;
+    const T* bface;
+    T* F;
+    StepArgs a;
+    int rpb;    // x rows per block (row kernel)
+    int seg;    // faces per thread (marching kernel)
+};
+
+// NONADV faces along D, one face per thread, both adjacent parabolas computed
+// by the thread (general fallback for any box)
+template <typename T, int D>
+struct BFacePair {
+    static constexpr int NT = NTH;
+    using Args = FaceArgs<T>;
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        int c = blk * NT + tid;
+        if (c >= g.n) return;
+        using V = Vars<D>;
+        int i, j, k;
+        decompose(g, c, i, j, k);
+        const size_t N = (size_t)g.n;
+        const T* W = A.W;
+        int idx[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
+        Side<T> L, R;
+#pragma unroll
+        for (int v = 0; v < 6; v++) {
+            const T* q = W + (size_t)V::f[v] * N;
+            Par<T> PL, PR;
+            parabola_pair(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], PL, PR);
+            side_left(PL, L, v);
+            side_right(PR, R, v);
+        }
+        T out[7];
+        face_solve(W[idx[2]], W[7 * N + idx[2]], W[(size_t)V::f[3] * N + idx[2]], W[(size_t)V::f[4] * N + idx[2]],
+                   W[idx[3]], W[7 * N + idx[3]], W[(size_t)V::f[3] * N + idx[3]],
+                   W[(size_t)V::f[4] * N + idx[3]], A.bface[c], L, R, T(A.a.gamma),
+                   T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+        store_face(A.F, N, c, out);
+    }
+};
+
+// NONADV faces along x with whole x rows per block: each thread computes the
+// parabolas of its own cell once; the left neighbour's side comes from LDS
+// (periodic wrap inside the row), so no parabola is computed twice.  Dynamic
+// LDS: NT * 18 values.
+template <typename T, int MAXT>
+struct BFaceXRows {
+    static constexpr int NT = MAXT;
+    using Args = FaceArgs<T>;
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        extern __shared__ unsigned char smem_raw[];
+        T* sm = reinterpret_cast<T*>(smem_raw);
+        using V = Vars<0>;
+        const Geo& g = A.g;
+        const size_t N = (size_t)g.n;
+        const int nx = g.nx;
+        const T* W = A.W;
+        int r = tid / nx;
+        int i = tid - r * nx;
+        int row = blk * A.rpb + r;
+        bool act = r < A.rpb && row < g.ny * g.nz;
+        int rowbase = row * nx;
+        Side<T> R;
+        if (act) {
+            int im2 = wrapc(i - 2, nx), im1 = wrapc(i - 1, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
+            T* mine = sm + (size_t)(r * nx + i) * 18;
+#pragma unroll
+            for (int v = 0; v < 6; v++) {
+                const T* q = W + (size_t)V::f[v] * N + rowbase;
+                Par<T> P = parabola(q[im2], q[im1], q[i], q[ip1], q[ip2]);
+                side_right(P, R, v);
+                mine[3 * v + 0] = P.qR;
+                mine[3 * v + 1] = P.dq;
+                mine[3 * v + 2] = P.q6;
+            }
+        }
+        __syncthreads();
+        if (!act) return;
+        int il = i == 0 ? nx - 1 : i - 1;
+        const T* left = sm + (size_t)(r * nx + il) * 18;
+        Side<T> L;
+#pragma unroll
+        for (int v = 0; v < 6; v++) {
+            L.e[v] = left[3 * v + 0];
+            L.dq[v] = left[3 * v + 1];
+            L.q6[v] = left[3 * v + 2];
+        }
+        int c = rowbase + i, cl = rowbase + il;
+        T out[7];
+        face_solve(W[cl], W[7 * N + cl], W[(size_t)V::f[3] * N + cl], W[(size_t)V::f[4] * N + cl], W[c],
+                   W[7 * N + c], W[(size_t)V::f[3] * N + c], W[(size_t)V::f[4] * N + c], A.bface[c], L, R,
+                   T(A.a.gamma), T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+        store_face(A.F, N, c, out);
+    }
+};
+
+// NONADV faces along D = y or z: each thread marches along one grid line over
+// a segment of `seg` faces with a sliding 5-cell window in registers, so each
+// cell's parabolas are computed once per segment (seg + 1 per seg faces);
+// threads are consecutive in x, so every load is coalesced.
+template <typename T, int D>
+struct BFaceMarch {
+    static constexpr int NT = NTH;
+    using Args = FaceArgs<T>;
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        using V = Vars<D>;
+        const Geo& g = A.g;
+        const size_t N = (size_t)g.n;
+        const T* W = A.W;
+        const int seg = A.seg;
+        const int nd = D == 1 ? g.ny : g.nz;
+        const int no = D == 1 ? g.nz : g.ny;
+        const int nseg = (nd + seg - 1) / seg;
+        int t = blk * NT + tid;
+        int i = t % g.nx;
+        int rest = t / g.nx;
+        int o = rest % no;
+        int sgi = rest / no;
+        if (sgi >= nseg) return;
+        const int base = D == 1 ? i + g.nxy * o : i + g.nx * o;
+        const int stride = D == 1 ? g.nx : g.nxy;
+        const int x0 = sgi * seg;
+        const int x1 = min(x0 + seg, nd);
+        const T gm = T(A.a.gamma);
+        const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
+
+        // window: w[v][m] = variable v of cell x-2+m; v = 0..5 parabola variables, 6 = rho
+        T w[7][5];
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            int cc = base + wrapc(x0 - 3 + m, nd) * stride;
+#pragma unroll
+            for (int v = 0; v < 6; v++) w[v][m] = W[(size_t)V::f[v] * N + cc];
+            w[6][m] = W[cc];
+        }
+        // parabolas of cell x0 - 1 (the left side of the first face)
+        Side<T> L;
+#pragma unroll
+        for (int v = 0; v < 6; v++) side_left(parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]), L, v);
+
+        for (int x = x0; x < x1; x++) {
+            int cn = base + wrapc(x + 2, nd) * stride;
+#pragma unroll
+            for (int v = 0; v < 7; v++) {
+#pragma unroll
+                for (int m = 0; m < 4; m++) w[v][m] = w[v][m + 1];
+                w[v][4] = W[(size_t)(v < 6 ? V::f[v] : 0) * N + cn];
+            }
+            Side<T> R, Ln;
+#pragma unroll
+            for (int v = 0; v < 6; v++) {
+                Par<T> P = parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]);
+                side_right(P, R, v);
+                side_left(P, Ln, v);
+            }
+            int c = base + x * stride;
+            T out[7];
+            // left cell x-1 is window slot 1, right cell x is slot 2
+            face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], A.bface[c], L, R,
+                       gm, ydx, out);
+            store_face(A.F, N, c, out);
+            L = Ln;
+        }
+    }
+};
+
+// NONADV update: flux differences, p dV work, face-field update from edge
+// fields (Sec. 2.5), Runge-Kutta combination (Sec. 2.2).  dbg != 0 writes
+// tau R(U) instead of the combination.
+template <typename T>
+struct BNonadvUpdate {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        CFields<T> U, S;
+        Fields<T> O;
+        const T* Fx;
+        const T* Fy;
+        const T* Fz;
+        StepArgs a;
+        RK rk;
+        int dbg;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        int c = blk * NT + tid;
+        if (c >= g.n) return;
+        int i, j, k;
+        decompose(g, c, i, j, k);
+        const size_t N = (size_t)g.n;
+        const T dtdx = T(step_dt(A.a) / A.a.h);
+        const T* Fx = A.Fx;
+        const T* Fy = A.Fy;
+        const T* Fz = A.Fz;
+        int xp = nbr<0>(g, c, i, j, k, 1), xm = nbr<0>(g, c, i, j, k, -1);
+        int yp = nbr<1>(g, c, i, j, k, 1), ym = nbr<1>(g, c, i, j, k, -1);
+        int zp = nbr<2>(g, c, i, j, k, 1), zm = nbr<2>(g, c, i, j, k, -1);
+        const T* Fd[3] = { Fx, Fy, Fz };
+        int up[3] = { xp, yp, zp };
+        T dF[3][5];
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int v = 0; v < 5; v++) dF[d][v] = Fd[d][v * N + up[d]] - Fd[d][v * N + c];
+        T inc[NF];
+        // momentum component a takes slot (a - d) mod 3 from direction d
+        inc[MX] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
+        inc[MY] = -dtdx * ((dF[0][1] + dF[1][0]) + dF[2][2]);
+        inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
+        inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
+        T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
+        inc[EI] = -T(A.a.gamma - 1.0) * A.U.f[EI][c] * dtdx * divv;
+
+        // edge fields (electric-field appendix): Ex at (i, j-1/2, k-1/2) from
+        // z faces at j-1, j and y faces at k, k-1; Ey at (i-1/2, j, k-1/2) from
+        // z faces at i-1, i and x faces at k-1, k; Ez at (i-1/2, j-1/2, k) from
+        // x faces at j-1, j and y faces at i-1, i.
+        const T* ezx = Fz + 5 * N;   // z faces, E along x
+        const T* ezy = Fz + 6 * N;   // z faces, E along y
+        const T* eyz = Fy + 5 * N;   // y faces, E along z
+        const T* eyx = Fy + 6 * N;   // y faces, E along x
+        const T* exy = Fx + 5 * N;   // x faces, E along y
+        const T* exz = Fx + 6 * N;   // x faces, E along z
+        auto Ex = [&](int cc, int cym, int czm) { return T(0.25) * (((ezx[cym] + ezx[cc]) + eyx[cc]) + eyx[czm]); };
+        auto Ey = [&](int cc, int cxm, int czm) { return T(0.25) * (((ezy[cxm] + ezy[cc]) + exy[czm]) + exy[cc]); };
+        auto Ez = [&](int cc, int cym, int cxm) { return T(0.25) * (((exz[cym] + exz[cc]) + eyz[cxm]) + eyz[cc]); };
+        int ip, jp, kp;
+        T Ex_c = Ex(c, ym, zm);
+        decompose(g, yp, ip, jp, kp);
+        T Ex_yp = Ex(yp, c, nbr<2>(g, yp, ip, jp, kp, -1));
+        decompose(g, zp, ip, jp, kp);
+        T Ex_zp = Ex(zp, nbr<1>(g, zp, ip, jp, kp, -1), c);
+        T Ey_c = Ey(c, xm, zm);
+        decompose(g, xp, ip, jp, kp);
+        T Ey_xp = Ey(xp, c, nbr<2>(g, xp, ip, jp, kp, -1));
+        decompose(g, zp, ip, jp, kp);
+        T Ey_zp = Ey(zp, nbr<0>(g, zp, ip, jp, kp, -1), c);
+        T Ez_c = Ez(c, ym, xm);
+        decompose(g, xp, ip, jp, kp);
+        T Ez_xp = Ez(xp, nbr<1>(g, xp, ip, jp, kp, -1), c);
+        decompose(g, yp, ip, jp, kp);
+        T Ez_yp = Ez(yp, c, nbr<0>(g, yp, ip, jp, kp, -1));
+        inc[BX] = -dtdx * (Ez_yp - Ez_c) + dtdx * (Ey_zp - Ey_c);
+        inc[BY] = -dtdx * (Ex_zp - Ex_c) + dtdx * (Ez_xp - Ez_c);
+        inc[BZ] = -dtdx * (Ey_xp - Ey_c) + dtdx * (Ex_yp - Ex_c);
+
+        const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
+        if (A.dbg) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
+            A.O.f[RHO][c] = T(0);
+            A.O.f[H2][c] = T(0);
+            return;
+        }
+        const T ra = T(A.rk.a), rb = T(A.rk.b);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            int f = upd[q];
+            T u = A.U.f[f][c];
+            A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc[f];
+        }
+    }
+};
+
+// ---------------------------------------------------------------- ADV
+
+// ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, 7 x N,
+// in the order rho, mx, my, mz, E, e, h2.
+template <typename T, int D>
+struct BAdvFace {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        CFields<T> U;
+        T* F;
+        StepArgs a;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        int c = blk * NT + tid;
+        if (c >= g.n) return;
+        int i, j, k;
+        decompose(g, c, i, j, k);
+        const size_t N = (size_t)g.n;
+        const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
+        int idx[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
+        T rl = A.U.f[RHO][idx[2]], rr = A.U.f[RHO][c];
+        T vl = A.U.f[MX + D][idx[2]] / rl;
+        T vr = A.U.f[MX + D][c] / rr;
+        T sl = sqrt(rl), sr = sqrt(rr);
+        T vf = (sl * vl + sr * vr) / (sl + sr);
+        bool upw = vf >= T(0);
+        T y = upw ? ydx * vf : ydx * (-vf);
+        const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            const T* u = A.U.f[fld[q]];
+            int o = upw ? 0 : 1;
+            T q0 = u[idx[o]], q1 = u[idx[o + 1]], q2 = u[idx[o + 2]], q3 = u[idx[o + 3]], q4 = u[idx[o + 4]];
+            Par<T> P = parabola(q0, q1, q2, q3, q4);
+            T qup = upw ? avg_right(P, y) : avg_left(P, y);
+            A.F[q * N + c] = vf * qup;
+        }
+    }
+};
+
+template <typename T>
+struct BAdvUpdate {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        CFields<T> U, S;
+        Fields<T> O;
+        const T* Fx;
+        const T* Fy;
+        const T* Fz;
+        StepArgs a;
+        RK rk;
+        int dbg;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        int c = blk * NT + tid;
+        if (c >= g.n) return;
+        int i, j, k;
+        decompose(g, c, i, j, k);
+        const size_t N = (size_t)g.n;
+        const T dtdx = T(step_dt(A.a) / A.a.h);
+        int xp = nbr<0>(g, c, i, j, k, 1), yp = nbr<1>(g, c, i, j, k, 1), zp = nbr<2>(g, c, i, j, k, 1);
+        const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
+        const T ra = T(A.rk.a), rb = T(A.rk.b);
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            T dx = A.Fx[q * N + xp] - A.Fx[q * N + c];
+            T dy = A.Fy[q * N + yp] - A.Fy[q * N + c];
+            T dz = A.Fz[q * N + zp] - A.Fz[q * N + c];
+            T inc = -dtdx * ((dx + dy) + dz);
+            int f = fld[q];
+            if (A.dbg) {
+                A.O.f[f][c] = inc;
+            } else {
+                T u = A.U.f[f][c];
+                A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc;
+            }
+        }
+        if (A.dbg) {
+            A.O.f[BX][c] = T(0);
+            A.O.f[BY][c] = T(0);
+            A.O.f[BZ][c] = T(0);
+        }
+    }
+};
+
+// ---------------------------------------------------------------- tail and reductions
+
+// Tail of the step (after ADV): H2 clamp to [0, rho], chemistry, dual-energy
+// sync (Sec. 2.8, pressure-gated), validity flag, per-block CFL speed maximum.
+// mode: 1 = full tail, 0 = speed only (state unchanged).
+template <typename T>
+struct BTail {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        Fields<T> U;
+        StepArgs a;
+        ChemArgs ch;
+        int mode;
+        double* part;
+        uint32_t* flags;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        int c = blk * NT + tid;
+        double spd = 0.0;
+        if (c < g.n) {
+            int i, j, k;
+            decompose(g, c, i, j, k);
+            const Fields<T>& U = A.U;
+            double rho = (double)U.f[RHO][c];
+            double mx = (double)U.f[MX][c], my = (double)U.f[MY][c], mz = (double)U.f[MZ][c];
+            double E = (double)U.f[EN][c];
+            double e = (double)U.f[EI][c];
+            double bx = 0.5 * ((double)U.f[BX][c] + (double)U.f[BX][nbr<0>(g, c, i, j, k, 1)]);
+            double by = 0.5 * ((double)U.f[BY][c] + (double)U.f[BY][nbr<1>(g, c, i, j, k, 1)]);
+            double bz = 0.5 * ((double)U.f[BZ][c] + (double)U.f[BZ][nbr<2>(g, c, i, j, k, 1)]);
+            if (A.mode == 1) {
+                double h2 = (double)U.f[H2][c];
+                h2 = h2 > rho ? rho : h2;
+                h2 = h2 < 0.0 ? 0.0 : h2;
+                if (A.ch.on) h2 = chem_h2(A.ch, A.a.gamma, rho, e, h2, step_dt(A.a));
+                double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+                double M = 0.5 * (bx * bx + by * by + bz * bz);
+                double ei = E - K - M;
+                if (ei >= 1e-3 * E && (A.a.gamma - 1.0) * ei > M) e = ei;
+                U.f[H2][c] = (T)h2;
+                U.f[EI][c] = (T)e;
+                e = (double)(T)e;
+            }
+            bool ok = rho > 0.0 && e > 0.0 && isfinite(rho) && isfinite(e) && isfinite(E) && isfinite(mx) &&
+                      isfinite(my) && isfinite(mz) && isfinite(bx) && isfinite(by) && isfinite(bz);
+            if (!ok) atomicOr(A.flags, 1u);
+            spd = ok ? cell_speed(A.a.gamma, rho, mx, my, mz, e, bx, by, bz) : 0.0;
+        }
+        block_max_store(spd, A.part, blk);
+    }
+};
+
+// dt = cfl h / max speed over the per-block maxima (max is exact, so the
+// result equals the minimum over cells of cfl h / speed)
+struct BReduceDt {
+    static constexpr int NT = 1024;
+    struct Args {
+        const double* part;
+        int nparts;
+        double cflh;
+        double* dt;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        __shared__ double red[16];
+        double m = 0.0;
+        for (int t = tid; t < A.nparts; t += NT) m = A.part[t] > m ? A.part[t] : m;
+        m = wave_max(m);
+        if ((tid & 63) == 0) red[tid >> 6] = m;
+        __syncthreads();
+        if (tid == 0) {
+            double r = red[0];
+            for (int w = 1; w < 16; w++) r = red[w] > r ? red[w] : r;
+            *A.dt = r > 0.0 ? A.cflh / r : 0.0;
+        }
+    }
+};
+
+// FP64 totals: per-block fixed-order sums of the 10 fields
+template <typename T>
+struct BTotalsPartial {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        CFields<T> U;
+        double* part;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        __shared__ double red[NF][NTH / 64];
+        int c = blk * NT + tid;
+        int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+        for (int f = 0; f < NF; f++) {
+            double v = c < A.g.n ? (double)A.U.f[f][c] : 0.0;
+            v = wave_sum(v);
+            if (lane == 0) red[f][wv] = v;
+        }
+        __syncthreads();
+        if (tid < NF) {
+            double s = 0.0;
+            for (int w = 0; w < NTH / 64; w++) s += red[tid][w];
+            A.part[(size_t)blk * NF + tid] = s;
+        }
+    }
+};
+
+struct BTotalsFinal {
+    static constexpr int NT = 1024;
+    struct Args {
+        const double* part;
+        int nparts;
+        double* out;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        __shared__ double red[NF][16];
+        int lane = tid & 63, wv = tid >> 6;
+        for (int f = 0; f < NF; f++) {
+            double s = 0.0;
+            for (int t = tid; t < A.nparts; t += NT) s += A.part[(size_t)t * NF + f];
+            s = wave_sum(s);
+            if (lane == 0) red[f][wv] = s;
+        }
+        __syncthreads();
+        if (tid < NF) {
+            double s = 0.0;
+            for (int w = 0; w < 16; w++) s += red[tid][w];
+            A.out[tid] = s;
+        }
+    }
+};
+
+// ---------------------------------------------------------------- state conversion
+
+// primitive (host order rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2) -> conserved
+template <typename T>
+struct BInit {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        const double* Wp;
+        Fields<T> U;
+        double gamma;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        int c = blk * NT + tid;
+        if (c >= g.n) return;
+        int i, j, k;
+        decompose(g, c, i, j, k);
+        const size_t N = (size_t)g.n;
+        const double* Wp = A.Wp;
+        double rho = Wp[c];
+        double vx = Wp[N + c], vy = Wp[2 * N + c], vz = Wp[3 * N + c];
+        double p = Wp[4 * N + c];
+        double bxf = Wp[5 * N + c], byf = Wp[6 * N + c], bzf = Wp[7 * N + c];
+        double bx = 0.5 * (bxf + Wp[5 * N + nbr<0>(g, c, i, j, k, 1)]);
+        double by = 0.5 * (byf + Wp[6 * N + nbr<1>(g, c, i, j, k, 1)]);
+        double bz = 0.5 * (bzf + Wp[7 * N + nbr<2>(g, c, i, j, k, 1)]);
+        double e = p / (A.gamma - 1.0);
+        A.U.f[RHO][c] = (T)rho;
+        A.U.f[MX][c] = (T)(rho * vx);
+        A.U.f[MY][c] = (T)(rho * vy);
+        A.U.f[MZ][c] = (T)(rho * vz);
+        A.U.f[EI][c] = (T)e;
+        A.U.f[EN][c] = (T)(e + 0.5 * rho * (vx * vx + vy * vy + vz * vz) + 0.5 * (bx * bx + by * by + bz * bz));
+        A.U.f[BX][c] = (T)bxf;
+        A.U.f[BY][c] = (T)byf;
+        A.U.f[BZ][c] = (T)bzf;
+        A.U.f[H2][c] = (T)(Wp[8 * N + c] * rho);
+    }
+};
+
+template <typename T>
+struct BFromF64 {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        const double* src;
+        Fields<T> U;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        int c = blk * NT + tid;
+        if (c >= A.g.n) return;
+        const size_t N = (size_t)A.g.n;
+#pragma unroll
+        for (int f = 0; f < NF; f++) A.U.f[f][c] = (T)A.src[f * N + c];
+    }
+};
+
+template <typename T>
+struct BToF64 {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        CFields<T> U;
+        double* dst;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        int c = blk * NT + tid;
+        if (c >= A.g.n) return;
+        const size_t N = (size_t)A.g.n;
+#pragma unroll
+        for (int f = 0; f < NF; f++) A.dst[f * N + c] = (double)A.U.f[f][c];
+    }
+};
+
+struct BClearFlags {
+    static constexpr int NT = 64;
+    struct Args {
+        uint32_t* flags;
+    };
+    static __device__ void run(const Args& A, int blk, int tid)
+    {
+        if (blk == 0 && tid == 0) *A.flags = 0u;
+    }
+};
+
+}  // namespace mhd

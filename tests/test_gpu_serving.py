@@ -1,0 +1,83 @@
+"""Serving on the GPU: merged multi-box launches give every box exactly the
+bits it gets alone (and the same bits as the single-box API), admission keeps
+the pool within the HBM budget, and a faulty request does not disturb the
+others."""
+import numpy as np
+import pytest
+
+from paper_1608_08748_amd import binding, inputs, serving
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+
+
+def _states():
+    return [inputs.turbulence(16, seed=31, mach=3.0, beta=1.0, x_h2=1e-3),
+            inputs.white_noise((8, 12, 20), seed=32, sigma=0.3, B=(0.2, 0.1, 0.0)),
+            inputs.turbulence(24, seed=33, mach=6.0, beta=0.3, x_h2=1e-2)]
+
+
+def _serve(states, precision, steps=3, budget=1 << 30, max_slots=8):
+    sv = binding.Server(budget, max_slots=max_slots, precision=precision)
+    out = serving.run(sv, states, steps, keep_state=True)
+    res = [sv.result(sv_id) for sv_id in [r["id"] for r in out["records"]]]
+    sv.close()
+    return out, res
+
+
+@pytest.mark.parametrize("precision", [binding.FP64, binding.FP32_MIXED])
+def test_alone_equals_mix_equals_single_box(precision):
+    states = _states()
+    mix, mix_res = _serve(states, precision)
+    assert mix["max_active"] == 3
+    for i, W in enumerate(states):
+        alone, alone_res = _serve([W], precision)
+        np.testing.assert_array_equal(alone_res[0], mix_res[i])
+        box = binding.Box(W.shape[1:], precision=precision)
+        box.init_state(W)
+        for _ in range(3):
+            box.step_cfl()
+        np.testing.assert_array_equal(box.get_state(), mix_res[i])
+        np.testing.assert_array_equal(box.totals(), mix["records"][i]["totals"])
+
+
+def test_budget_limits_boxes_in_flight():
+    states = [inputs.turbulence(16, seed=40 + k, mach=2.0, beta=1.0, x_h2=1e-3) for k in range(6)]
+    p = binding.server_params(precision=binding.FP32_MIXED)
+    per_box = binding.server_box_bytes(p, (16, 16, 16))
+    sv = binding.Server(2 * per_box + 1024, max_slots=8, precision=binding.FP32_MIXED)
+    out = serving.run(sv, states, 4)
+    used, peak, cap = sv.memory()
+    sv.close()
+    assert out["statuses"] == [0]
+    assert out["max_active"] == 2
+    assert peak <= cap and peak == 2 * per_box and used == 0
+
+
+def test_faulty_request_is_isolated():
+    states = _states()
+    bad = states[1].copy()
+    bad[0, 2, 3, 4] = np.nan
+    mix, mix_res = _serve([states[0], bad, states[2]], binding.FP64)
+    assert mix["records"][1]["status"] == binding.MHD_ENONPHYS
+    assert mix["records"][0]["status"] == 0 and mix["records"][2]["status"] == 0
+    clean, clean_res = _serve([states[0], states[2]], binding.FP64)
+    np.testing.assert_array_equal(clean_res[0], mix_res[0])
+    np.testing.assert_array_equal(clean_res[1], mix_res[2])
+
+
+def test_poisson_arrivals_complete():
+    states = [inputs.turbulence(n, seed=50 + n, mach=4.0, beta=0.5, x_h2=1e-3) for n in (16, 24, 32, 16, 24)]
+    sv = binding.Server(1 << 30, max_slots=3, precision=binding.FP32_MIXED)
+    out = serving.run(sv, states, 5, arrivals=serving.poisson_arrivals(len(states), 50.0, seed=5))
+    sv.close()
+    assert out["statuses"] == [0]
+    assert out["max_active"] <= 3
+    assert out["latency_p99"] >= out["latency_p50"] > 0
