@@ -25,8 +25,6 @@ __device__ __forceinline__ double step_dt(const StepArgs& a)
 
 struct RK { double a, b; };
 
-struct ChemArgs;
-
 // ---------------------------------------------------------------- launch wrappers
 
 template <class Body>
@@ -46,7 +44,8 @@ __global__ __launch_bounds__(Body::NT) void k_many(const typename Body::Args* __
         if (bstart[mid] <= blk) lo = mid;
         else hi = mid - 1;
     }
-    Body::run(tab[lo], blk - bstart[lo], (int)threadIdx.x);
+    const typename Body::Args a = tab[lo];
+    Body::run(a, blk - bstart[lo], (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------- NONADV
@@ -63,7 +62,7 @@ struct BPrim {
         uint32_t* flags;
         const double* dt_cfl;   // non-null: check the explicit dt against it
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
         int c = blk * NT + tid;
@@ -118,7 +117,7 @@ template <typename T, int D>
 struct BFacePair {
     static constexpr int NT = NTH;
     using Args = FaceArgs<T>;
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
         int c = blk * NT + tid;
@@ -157,7 +156,7 @@ template <typename T, int MAXT>
 struct BFaceXRows {
     static constexpr int NT = MAXT;
     using Args = FaceArgs<T>;
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         extern __shared__ unsigned char smem_raw[];
         T* sm = reinterpret_cast<T*>(smem_raw);
@@ -213,7 +212,7 @@ template <typename T, int D>
 struct BFaceMarch {
     static constexpr int NT = NTH;
     using Args = FaceArgs<T>;
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         using V = Vars<D>;
         const Geo& g = A.g;
@@ -293,7 +292,7 @@ struct BNonadvUpdate {
         RK rk;
         int dbg;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
         int c = blk * NT + tid;
@@ -388,7 +387,7 @@ struct BAdvFace {
         T* F;
         StepArgs a;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
         int c = blk * NT + tid;
@@ -434,7 +433,7 @@ struct BAdvUpdate {
         RK rk;
         int dbg;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
         int c = blk * NT + tid;
@@ -485,7 +484,7 @@ struct BTail {
         double* part;
         uint32_t* flags;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
         int c = blk * NT + tid;
@@ -533,7 +532,7 @@ struct BReduceDt {
         double cflh;
         double* dt;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         __shared__ double red[16];
         double m = 0.0;
@@ -558,7 +557,7 @@ struct BTotalsPartial {
         CFields<T> U;
         double* part;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         __shared__ double red[NF][NTH / 64];
         int c = blk * NT + tid;
@@ -585,7 +584,7 @@ struct BTotalsFinal {
         int nparts;
         double* out;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         __shared__ double red[NF][16];
         int lane = tid & 63, wv = tid >> 6;
@@ -616,7 +615,7 @@ struct BInit {
         Fields<T> U;
         double gamma;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
         int c = blk * NT + tid;
@@ -654,7 +653,7 @@ struct BFromF64 {
         const double* src;
         Fields<T> U;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         int c = blk * NT + tid;
         if (c >= A.g.n) return;
@@ -672,7 +671,7 @@ struct BToF64 {
         CFields<T> U;
         double* dst;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         int c = blk * NT + tid;
         if (c >= A.g.n) return;
@@ -687,7 +686,7 @@ struct BClearFlags {
     struct Args {
         uint32_t* flags;
     };
-    static __device__ void run(const Args& A, int blk, int tid)
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         if (blk == 0 && tid == 0) *A.flags = 0u;
     }
