@@ -14,6 +14,7 @@ Workloads (synthetic, seeded; see paper_1608_08748_amd/inputs.py):
   c3  512^3 FP32 state (FP64 chemistry / reductions), rms Mach 5, beta 0.3,
       seed 3, with the FP64 run of the same seed and dt sequence for the error
   c1  32^3 FP64 white-noise box (the oracle's own configuration)
+  c4  1024^3 FP32 single box (about 253 GB of HBM), conservation over the run
   c5  serving: 256 boxes of {32..128}^3 with Poisson arrivals, p50/p99 latency
 
 Prints one JSON line.
@@ -155,12 +156,79 @@ def _serving_bench(args):
     }
 
 
+def _largest_box_bench(args):
+    """c4: one 1024^3 FP32 box (three state copies of 10 fields = 129 GB plus
+    scratch, about 253 GB of HBM), lognormal density, rms Mach 10, beta 0.1.
+    There is no FP64 twin at this size (it would need twice the memory); the
+    full-size checks are the properties that hold at any size: conservation of
+    mass, momentum, energy and face flux over the run, finiteness and
+    positivity (latched faults)."""
+    import numpy as np
+    import torch
+    from paper_1608_08748_amd import binding, inputs
+    steps = args.steps if args.steps is not None else 50
+    n = 1024
+    torch.cuda.set_device(0)
+
+    def log(msg):
+        print("c4: " + msg, file=sys.stderr, flush=True)
+
+    # warm-up on a small box (kernel loading)
+    wb = binding.Box((64, 64, 64), precision=binding.FP32_MIXED)
+    wb.init_state(inputs.c4(n=64))
+    for _ in range(max(args.warmup, 1)):
+        wb.step(wb.cfl_dt())
+    wb.close()
+    del wb
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    log("device memory free %.1f GB of %.1f GB" % (free / 1e9, total / 1e9))
+    t = time.perf_counter()
+    W = inputs.c4(n=n, log=log)
+    log("initial condition generated in %.1f s" % (time.perf_counter() - t))
+    box = binding.Box((n, n, n), precision=binding.FP32_MIXED)
+    log("workspace %.1f GB" % (box.ws.numel() / 1e9))
+    box.init_state(W)
+    del W
+    t0 = box.totals()
+    box.set_timing(True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for s in range(steps):
+        box.step(box.cfl_dt())
+        if s % 10 == 9:
+            log("step %d" % (s + 1))
+    box.cfl_dt()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ts
+    timing = box.get_timing()
+    box.set_timing(False)
+    t1 = box.totals()
+    ncell = n ** 3
+    drift = {binding.FIELDS[f]: float(abs(t1[f] - t0[f]) / max(abs(t0[f]), 1e-300)) for f in (0, 4, 6)}
+    for f in (1, 2, 3, 7, 8):   # zero-mean fields: relative to the cell count
+        drift[binding.FIELDS[f]] = float(abs(t1[f] - t0[f]) / ncell)
+    return {
+        "metric": METRIC, "value": round(ncell * steps / el, 1), "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(el / steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "c4: 1024^3 periodic MHD turbulence, lognormal density sigma 1, rms Mach 10, "
+                               "beta 0.1, x_H2 1e-2, FP32 state/fluxes, FP64 chemistry/regularisation/CFL/totals",
+                   "cells": ncell, "grid": [n, n, n], "workspace_bytes": int(box.ws.numel()),
+                   "parallelism": "single GPU"},
+        "roofline": _roofline(timing, ncell, 4),
+        "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
+        "conservation_drift": drift,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -176,6 +244,9 @@ def main():
 
     if args.config == "c5":
         print(json.dumps(_serving_bench(args)), flush=True)
+        return
+    if args.config == "c4":
+        print(json.dumps(_largest_box_bench(args)), flush=True)
         return
 
     cfg = _config(args.config)

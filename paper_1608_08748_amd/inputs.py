@@ -58,45 +58,62 @@ def _spectral_field(rng, shape, kmin=1, kmax=8, slope=-2.0, dtype=np.float64):
     shells kmin <= |k| <= kmax, unit variance."""
     import scipy.fft as sfft
     nz, ny, nx = shape
-    kz = np.fft.fftfreq(nz, 1.0 / nz)[:, None, None]
-    ky = np.fft.fftfreq(ny, 1.0 / ny)[None, :, None]
-    kx = np.arange(nx // 2 + 1, dtype=np.float64)[None, None, :]
+    rdt = np.float32 if dtype == np.float32 else np.float64
+    cdt = np.complex64 if dtype == np.float32 else np.complex128
+    kz = np.fft.fftfreq(nz, 1.0 / nz).astype(rdt)[:, None, None]
+    ky = np.fft.fftfreq(ny, 1.0 / ny).astype(rdt)[None, :, None]
+    kx = np.arange(nx // 2 + 1, dtype=rdt)[None, None, :]
     kk = np.sqrt(kx * kx + ky * ky + kz * kz)
     shell = np.rint(kk)
     mask = (shell >= kmin) & (shell <= kmax) & (kk > 0)
+    del shell
     # E(k) ~ k^slope in a shell of area ~k^2 means |a_k|^2 ~ k^(slope-2)
     amp = np.zeros_like(kk)
     amp[mask] = kk[mask] ** ((slope - 2.0) / 2.0)
-    cdt = np.complex64 if dtype == np.float32 else np.complex128
-    spec = (rng.standard_normal(kk.shape) + 1j * rng.standard_normal(kk.shape)).astype(cdt)
-    spec *= amp.astype(spec.real.dtype)
-    f = sfft.irfftn(spec, s=(nz, ny, nx), axes=(0, 1, 2), workers=-1)
-    f = f - f.mean()
-    s = float(np.sqrt(np.mean(f.astype(np.float64) ** 2)))
+    del kk, mask
+    spec = np.empty(amp.shape, dtype=cdt)
+    spec.real = rng.standard_normal(amp.shape, dtype=rdt)
+    spec.imag = rng.standard_normal(amp.shape, dtype=rdt)
+    spec *= amp
+    del amp
+    f = sfft.irfftn(spec, s=(nz, ny, nx), axes=(0, 1, 2), workers=-1, overwrite_x=True)
+    del spec
+    f -= f.mean(dtype=np.float64)
+    s = float(np.sqrt(np.mean(np.square(f, dtype=np.float64))))
     if s > 0:
-        f = f / s
-    return f.astype(np.float64)
+        f /= s
+    return f
 
 
-def turbulence(n, seed, mach, beta, x_h2, lognormal_sigma=None, rho0=1.0, p0=1.0, gamma=5.0 / 3.0):
+def turbulence(n, seed, mach, beta, x_h2, lognormal_sigma=None, rho0=1.0, p0=1.0, gamma=5.0 / 3.0, log=None):
     """Supersonic MHD turbulence start: GRF velocity (k^-2, k = 1..8) at rms
     Mach ``mach``, mean field B0 = sqrt(2 p0 / beta) along x, isothermal
-    pressure p = p0 rho / rho0, optional lognormal density of width sigma."""
+    pressure p = p0 rho / rho0, optional lognormal density of width sigma.
+    ``log``: optional callable given a progress string after each field."""
     shape = (n, n, n)
     rng = np.random.default_rng(seed)
+    # boxes of 512^3 and more draw their random fields in single precision
+    dt = np.float32 if n >= 512 else np.float64
     W = _alloc(shape)
     if lognormal_sigma is None:
         W[0] = rho0
     else:
-        g = _spectral_field(rng, shape)
+        g = _spectral_field(rng, shape, dtype=dt)
         s = float(lognormal_sigma)
-        rho = np.exp(s * g - 0.5 * s * s)
-        W[0] = rho0 * rho / rho.mean()
-    vel = np.stack([_spectral_field(rng, shape) for _ in range(3)])
-    vrms = np.sqrt(np.mean(np.sum(vel * vel, axis=0)))
+        W[0] = np.exp(s * g - 0.5 * s * s)
+        del g
+        W[0] *= rho0 / W[0].mean()
+        if log:
+            log("density done")
+    ms = 0.0
+    for d in range(3):
+        W[1 + d] = _spectral_field(rng, shape, dtype=dt)
+        ms += float(np.mean(np.square(W[1 + d])))
+        if log:
+            log("velocity %d done" % d)
     cs0 = np.sqrt(gamma * p0 / rho0)
-    W[1:4] = vel * (mach * cs0 / vrms)
-    W[4] = p0 * W[0] / rho0
+    W[1:4] *= mach * cs0 / np.sqrt(ms)
+    np.multiply(W[0], p0 / rho0, out=W[4])
     W[5] = np.sqrt(2.0 * p0 / beta)
     W[8] = x_h2
     return W
@@ -112,9 +129,9 @@ def c3(n=512, seed=3):
     return turbulence(n, seed, mach=5.0, beta=0.3, x_h2=1e-3)
 
 
-def c4(n=1024, seed=4):
+def c4(n=1024, seed=4, log=None):
     """1024^3, lognormal density (sigma 1), rms Mach 10, beta = 0.1, x_H2 = 1e-2."""
-    return turbulence(n, seed, mach=10.0, beta=0.1, x_h2=1e-2, lognormal_sigma=1.0)
+    return turbulence(n, seed, mach=10.0, beta=0.1, x_h2=1e-2, lognormal_sigma=1.0, log=log)
 
 
 def serving_requests(count=256, seed=5, sizes=(32, 48, 64, 96, 128), rate=None):

@@ -256,9 +256,14 @@ def test_fault_flags():
         box.step(-1.0)
 
 
-def test_fp32_mixed_against_fp64():
+@pytest.mark.parametrize("recipe", ["c3", "c4"])
+def test_fp32_mixed_against_fp64(recipe):
     # precision form at a small size: totals of the FP32-state path within 1e-5
-    W = inputs.turbulence(48, seed=3, mach=5.0, beta=0.3, x_h2=1e-3)
+    # (c3 recipe: rms Mach 5, beta 0.3; c4 recipe: lognormal density, Mach 10, beta 0.1)
+    if recipe == "c3":
+        W = inputs.turbulence(48, seed=3, mach=5.0, beta=0.3, x_h2=1e-3)
+    else:
+        W = inputs.c4(n=48)
     shape = W.shape[1:]
     a = binding.Box(shape, precision=binding.FP64)
     b = binding.Box(shape, precision=binding.FP32_MIXED)
