@@ -408,19 +408,21 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
     emit_adv_face<T, 0>(b, e, in, a);
     emit_adv_face<T, 1>(b, e, in, a);
-    emit_adv_face<T, 2>(b, e, in, a);
-    typename BAdvUpdate<T>::Args ua;
+    // z faces marched together with the update of every cell
+    constexpr int ADV_SEG = 32;
+    typename BAdvZUpdate<T>::Args ua;
     ua.g = b->g;
     ua.U = cview(in);
     ua.S = cview(S);
     ua.O = out;
     ua.Fx = reinterpret_cast<T*>(b->F[0]);
     ua.Fy = reinterpret_cast<T*>(b->F[1]);
-    ua.Fz = reinterpret_cast<T*>(b->F[2]);
     ua.a = a;
     ua.rk = rk;
     ua.dbg = dbg;
-    e.template launch<BAdvUpdate<T>>(MHD_K_ADV_UPDATE, b->nblocks, 0, ua);
+    ua.seg = b->g.nz < ADV_SEG ? b->g.nz : ADV_SEG;
+    long long threads = (long long)b->g.nx * b->g.ny * ((b->g.nz + ua.seg - 1) / ua.seg);
+    e.template launch<BAdvZUpdate<T>>(MHD_K_ADV_UPDATE, (int)((threads + NTH - 1) / NTH), 0, ua);
 }
 
 // NONADV stage: the M and B groups each rotate through their three slots

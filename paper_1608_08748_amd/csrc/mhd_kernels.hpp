@@ -419,6 +419,124 @@ struct BAdvFace {
     }
 };
 
+// ADV z faces fused with the ADV update: each thread marches along z over a
+// segment of cells with a sliding 6-cell window of the 7 advected fields, so
+// the flux at the upper z face of cell k is the lower one of cell k+1, and the
+// update reads the x and y fluxes written by the x/y face kernels.  Same
+// arithmetic as BAdvFace<T,2> followed by BAdvUpdate.
+template <typename T>
+struct BAdvZUpdate {
+    static constexpr int NT = NTH;
+    struct Args {
+        Geo g;
+        CFields<T> U, S;
+        Fields<T> O;
+        const T* Fx;
+        const T* Fy;
+        StepArgs a;
+        RK rk;
+        int dbg;
+        int seg;
+    };
+    // flux of the 7 fields through the face between window cells m and m+1
+    // (window cell m is z index k-2+m)
+    static __device__ __forceinline__ void zflux(const T w[7][6], int m, T ydx, T out[7])
+    {
+        T rl = w[0][m], rr = w[0][m + 1];
+        T vl = w[3][m] / rl;
+        T vr = w[3][m + 1] / rr;
+        T sl = sqrt(rl), sr = sqrt(rr);
+        T vf = (sl * vl + sr * vr) / (sl + sr);
+        bool upw = vf >= T(0);
+        T y = upw ? ydx * vf : ydx * (-vf);
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            // upwind cell m (window m-2..m+2) or m+1 (window m-1..m+3)
+            T q0 = upw ? w[q][m - 2] : w[q][m - 1];
+            T q1 = upw ? w[q][m - 1] : w[q][m];
+            T q2 = upw ? w[q][m] : w[q][m + 1];
+            T q3 = upw ? w[q][m + 1] : w[q][m + 2];
+            T q4 = upw ? w[q][m + 2] : w[q][m + 3];
+            Par<T> P = parabola(q0, q1, q2, q3, q4);
+            T qup = upw ? avg_right(P, y) : avg_left(P, y);
+            out[q] = vf * qup;
+        }
+    }
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        const int seg = A.seg;
+        const int nd = g.nz;
+        const int nseg = (nd + seg - 1) / seg;
+        int t = blk * NT + tid;
+        int i = t % g.nx;
+        int rest = t / g.nx;
+        int j = rest % g.ny;
+        int sgi = rest / g.ny;
+        if (sgi >= nseg) return;
+        const size_t N = (size_t)g.n;
+        const int base = i + g.nx * j;
+        const int stride = g.nxy;
+        const int x0 = sgi * seg;
+        const int x1 = min(x0 + seg, nd);
+        const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
+        const T dtdx = T(step_dt(A.a) / A.a.h);
+        const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
+        const T ra = T(A.rk.a), rb = T(A.rk.b);
+        int ip = i + 1 == g.nx ? 0 : i + 1;
+        int jp = j + 1 == g.ny ? 0 : j + 1;
+
+        // window cells z = x0-3 .. x0+2 (slots 0..5): the first face is x0-1/2
+        T w[7][6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) {
+            int cc = base + wrapc(x0 - 3 + m, nd) * stride;
+#pragma unroll
+            for (int q = 0; q < 7; q++) w[q][m] = A.U.f[fld[q]][cc];
+        }
+        // face between window slots 2 and 3 = cells x0-1 and x0; parabola
+        // stencils use slots 0..4 or 1..5
+        T Flo[7];
+        zflux(w, 2, ydx, Flo);
+        for (int x = x0; x < x1; x++) {
+            // slide: window slots 0..5 = cells x-2 .. x+3
+            int cn = base + wrapc(x + 3, nd) * stride;
+#pragma unroll
+            for (int q = 0; q < 7; q++) {
+#pragma unroll
+                for (int m = 0; m < 5; m++) w[q][m] = w[q][m + 1];
+                w[q][5] = A.U.f[fld[q]][cn];
+            }
+            // upper face of cell x: between slots 2 (cell x) and 3 (cell x+1)
+            T Fup[7];
+            zflux(w, 2, ydx, Fup);
+            int c = base + x * stride;
+            int cxp = c - i + ip;
+            int cyp = c + (jp - j) * g.nx;
+#pragma unroll
+            for (int q = 0; q < 7; q++) {
+                T dx = A.Fx[q * N + cxp] - A.Fx[q * N + c];
+                T dy = A.Fy[q * N + cyp] - A.Fy[q * N + c];
+                T dz = Fup[q] - Flo[q];
+                T inc = -dtdx * ((dx + dy) + dz);
+                int f = fld[q];
+                if (A.dbg) {
+                    A.O.f[f][c] = inc;
+                } else {
+                    T u = w[q][2];
+                    A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc;
+                }
+                Flo[q] = Fup[q];
+            }
+            if (A.dbg) {
+                A.O.f[BX][c] = T(0);
+                A.O.f[BY][c] = T(0);
+                A.O.f[BZ][c] = T(0);
+            }
+        }
+    }
+};
+
 template <typename T>
 struct BAdvUpdate {
     static constexpr int NT = NTH;
