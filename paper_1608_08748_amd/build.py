@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libmhdchem.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
