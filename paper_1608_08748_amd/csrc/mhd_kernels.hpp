@@ -27,17 +27,28 @@ struct RK { double a, b; };
 
 // ---------------------------------------------------------------- launch wrappers
 
+// Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD
+// b % 8) and each XCD has its own L2.  This bijection gives every XCD one
+// contiguous range of logical blocks, so stencil neighbours in the next row
+// or plane are read through the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    constexpr int X = 8;
+    int q = nb / X, r = nb % X, x = b % X, i = b / X;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 template <class Body>
 __global__ __launch_bounds__(Body::NT) void k_one(typename Body::Args a)
 {
-    Body::run(a, (int)blockIdx.x, (int)threadIdx.x);
+    Body::run(a, xcd_block((int)blockIdx.x, (int)gridDim.x), (int)threadIdx.x);
 }
 
 template <class Body>
 __global__ __launch_bounds__(Body::NT) void k_many(const typename Body::Args* __restrict__ tab,
                                                    const int* __restrict__ bstart, int nbox)
 {
-    int blk = (int)blockIdx.x;
+    int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
     int lo = 0, hi = nbox - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
