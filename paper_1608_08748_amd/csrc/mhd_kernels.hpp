@@ -38,17 +38,25 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// kernels whose stencil spans neighbouring rows of other blocks opt in with
+// `static constexpr bool XCD = true`
+template <class Body>
+__device__ __forceinline__ int logical_block()
+{
+    return Body::XCD ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+}
+
 template <class Body>
 __global__ __launch_bounds__(Body::NT) void k_one(typename Body::Args a)
 {
-    Body::run(a, xcd_block((int)blockIdx.x, (int)gridDim.x), (int)threadIdx.x);
+    Body::run(a, logical_block<Body>(), (int)threadIdx.x);
 }
 
 template <class Body>
 __global__ __launch_bounds__(Body::NT) void k_many(const typename Body::Args* __restrict__ tab,
                                                    const int* __restrict__ bstart, int nbox)
 {
-    int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    int blk = logical_block<Body>();
     int lo = 0, hi = nbox - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -65,6 +73,7 @@ __global__ __launch_bounds__(Body::NT) void k_many(const typename Body::Args* __
 template <typename T>
 struct BPrim {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         CFields<T> U;
@@ -127,6 +136,7 @@ struct FaceArgs {
 template <typename T, int D>
 struct BFacePair {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     using Args = FaceArgs<T>;
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -166,6 +176,7 @@ struct BFacePair {
 template <typename T, int MAXT>
 struct BFaceXRows {
     static constexpr int NT = MAXT;
+    static constexpr bool XCD = false;
     using Args = FaceArgs<T>;
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -222,6 +233,7 @@ struct BFaceXRows {
 template <typename T, int D>
 struct BFaceMarch {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     using Args = FaceArgs<T>;
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -292,6 +304,7 @@ struct BFaceMarch {
 template <typename T>
 struct BNonadvUpdate {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         CFields<T> U, S;
@@ -392,6 +405,7 @@ struct BNonadvUpdate {
 template <typename T, int D>
 struct BAdvFace {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = D == 1;   // the y stencil reads rows of neighbouring blocks
     struct Args {
         Geo g;
         CFields<T> U;
@@ -438,6 +452,7 @@ struct BAdvFace {
 template <typename T>
 struct BAdvZUpdate {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         CFields<T> U, S;
@@ -551,6 +566,7 @@ struct BAdvZUpdate {
 template <typename T>
 struct BAdvUpdate {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         CFields<T> U, S;
@@ -604,6 +620,7 @@ struct BAdvUpdate {
 template <typename T>
 struct BTail {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         Fields<T> U;
@@ -655,6 +672,7 @@ struct BTail {
 // result equals the minimum over cells of cfl h / speed)
 struct BReduceDt {
     static constexpr int NT = 1024;
+    static constexpr bool XCD = false;
     struct Args {
         const double* part;
         int nparts;
@@ -681,6 +699,7 @@ struct BReduceDt {
 template <typename T>
 struct BTotalsPartial {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         CFields<T> U;
@@ -708,6 +727,7 @@ struct BTotalsPartial {
 
 struct BTotalsFinal {
     static constexpr int NT = 1024;
+    static constexpr bool XCD = false;
     struct Args {
         const double* part;
         int nparts;
@@ -738,6 +758,7 @@ struct BTotalsFinal {
 template <typename T>
 struct BInit {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         const double* Wp;
@@ -777,6 +798,7 @@ struct BInit {
 template <typename T>
 struct BFromF64 {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         const double* src;
@@ -795,6 +817,7 @@ struct BFromF64 {
 template <typename T>
 struct BToF64 {
     static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         CFields<T> U;
@@ -812,6 +835,7 @@ struct BToF64 {
 
 struct BClearFlags {
     static constexpr int NT = 64;
+    static constexpr bool XCD = false;
     struct Args {
         uint32_t* flags;
     };
