@@ -84,15 +84,50 @@ def _timed_run(box, steps, dts=None):
     return time.perf_counter() - t0, used
 
 
-def _roofline(timing, ncell, esz):
+# algorithmic floating-point operations per face of the NONADV face kernels
+# (six parabolas of one cell, about 93 each, plus the face solve: averages,
+# eigen-structure, 36 parabola averages, characteristic amplitudes, projector
+# sum and fluxes, about 366; a square root or a division counts as one)
+ALG_FLOPS = {"nonadv_face": 6 * 93 + 366}
+# published MI355X vector peaks (TFLOP/s) and HBM peak
+VALU_PEAK_TF = {8: 78.6, 4: 157.3}
+
+# HBM traffic of the dominant kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs, keyed by (workload, precision, kernel) and by a hash of
+# the kernel sources at the time the counters were taken; FETCH_SIZE is scaled
+# by 2 and WRITE_SIZE by 1, the factors that make a 1 GiB device copy read and
+# write 1 GiB
+TRAFFIC = {}
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mhd_math.hpp", "mhd_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1608_08748_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _roofline(timing, ncell, esz, workload):
     name, (ms, cnt) = max(((k, v) for k, v in timing.items() if k in ALG_VALUES), key=lambda kv: kv[1][0])
     avg_s = ms / cnt / 1e3
     alg_bytes = ALG_VALUES[name] * esz * ncell
     gbs = alg_bytes / avg_s / 1e9
-    return {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_ms": round(ms / cnt, 4), "launches": cnt,
-            "alg_bytes_per_launch": alg_bytes}
+    tr = TRAFFIC.get((workload, esz, name))
+    traffic = tr[1] if tr is not None and tr[0] == _kernel_source_hash() else None
+    out = {"kernel": name, "avg_launch_ms": round(ms / cnt, 4), "launches": cnt, "traffic": traffic,
+           "alg_bytes_per_launch": alg_bytes, "hbm_achieved_gbs": round(gbs, 1),
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if name in ALG_FLOPS:
+        # one face per cell per launch
+        tf = ALG_FLOPS[name] * ncell / avg_s / 1e12
+        out.update({"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TF[esz], "unit": "TFLOP/s",
+                    "frac": round(tf / VALU_PEAK_TF[esz], 4), "alg_flops_per_launch": ALG_FLOPS[name] * ncell})
+    else:
+        out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return out
 
 
 def _cpu_baseline(n=192, steps=3):
@@ -228,7 +263,7 @@ def _largest_box_bench(args):
                                "beta 0.1, x_H2 1e-2, FP32 state/fluxes, FP64 chemistry/regularisation/CFL/totals",
                    "cells": ncell, "grid": [n, n, n], "workspace_bytes": int(box.ws.numel()),
                    "parallelism": "single GPU"},
-        "roofline": _roofline(timing, ncell, 4),
+        "roofline": _roofline(timing, ncell, 4, "c4"),
         "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
         "conservation_drift": drift,
     }
@@ -304,7 +339,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "cells": ncell, "grid": list(shape)[::-1], "cfl": 0.3,
                    "gamma": 5.0 / 3.0, "theta": 1.0, "parallelism": "single GPU"},
-        "roofline": _roofline(timing, ncell, esz),
+        "roofline": _roofline(timing, ncell, esz, args.config),
         "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
     }
     tot = box.totals()
