@@ -267,10 +267,24 @@ struct BFaceMarch {
             for (int v = 0; v < 6; v++) w[v][m] = W[(size_t)V::f[v] * N + cc];
             w[6][m] = W[cc];
         }
-        // parabolas of cell x0 - 1 (the left side of the first face)
+        // parabolas of cell x0 - 1 (the left side of the first face).  Along
+        // the march each cell's limited slope and each face's interface value
+        // is computed once and carried: dmc = slope of the current cell,
+        // fl = interface value at its lower face (Step 1, the same calls as
+        // in parabola())
         Side<T> L;
+        T dmc[6], fl[6];
 #pragma unroll
-        for (int v = 0; v < 6; v++) side_left(parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]), L, v);
+        for (int v = 0; v < 6; v++) {
+            T d0 = limited_slope(w[v][0], w[v][1], w[v][2]);
+            T d1 = limited_slope(w[v][1], w[v][2], w[v][3]);
+            T d2 = limited_slope(w[v][2], w[v][3], w[v][4]);
+            T f0 = interface_value(w[v][1], w[v][2], d0, d1);
+            T f1 = interface_value(w[v][2], w[v][3], d1, d2);
+            side_left(parabola_finish(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4], f0, f1, d1), L, v);
+            dmc[v] = d2;
+            fl[v] = f1;
+        }
 
         for (int x = x0; x < x1; x++) {
             int cn = base + wrapc(x + 2, nd) * stride;
@@ -283,9 +297,14 @@ struct BFaceMarch {
             Side<T> R, Ln;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                Par<T> P = parabola(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]);
+                // window slots 0..4 = cells x-2 .. x+2
+                T dn = limited_slope(w[v][2], w[v][3], w[v][4]);
+                T fr = interface_value(w[v][2], w[v][3], dmc[v], dn);
+                Par<T> P = parabola_finish(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4], fl[v], fr, dmc[v]);
                 side_right(P, R, v);
                 side_left(P, Ln, v);
+                dmc[v] = dn;
+                fl[v] = fr;
             }
             int c = base + x * stride;
             T out[7];
@@ -424,11 +443,10 @@ struct BAdvFace {
         int idx[6];
 #pragma unroll
         for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
+        // sqrt(rho)-weighted face velocity; sqrt(rho) v = m / sqrt(rho)
         T rl = A.U.f[RHO][idx[2]], rr = A.U.f[RHO][c];
-        T vl = A.U.f[MX + D][idx[2]] / rl;
-        T vr = A.U.f[MX + D][c] / rr;
-        T sl = sqrt(rl), sr = sqrt(rr);
-        T vf = (sl * vl + sr * vr) / (sl + sr);
+        T rsl = rsqrt_nr(rl), rsr = rsqrt_nr(rr);
+        T vf = (A.U.f[MX + D][idx[2]] * rsl + A.U.f[MX + D][c] * rsr) * rcp_nr(rl * rsl + rr * rsr);
         bool upw = vf >= T(0);
         T y = upw ? ydx * vf : ydx * (-vf);
         const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
@@ -469,10 +487,8 @@ struct BAdvZUpdate {
     static __device__ __forceinline__ void zflux(const T w[7][6], int m, T ydx, T out[7])
     {
         T rl = w[0][m], rr = w[0][m + 1];
-        T vl = w[3][m] / rl;
-        T vr = w[3][m + 1] / rr;
-        T sl = sqrt(rl), sr = sqrt(rr);
-        T vf = (sl * vl + sr * vr) / (sl + sr);
+        T rsl = rsqrt_nr(rl), rsr = rsqrt_nr(rr);
+        T vf = (w[3][m] * rsl + w[3][m + 1] * rsr) * rcp_nr(rl * rsl + rr * rsr);
         bool upw = vf >= T(0);
         T y = upw ? ydx * vf : ydx * (-vf);
 #pragma unroll

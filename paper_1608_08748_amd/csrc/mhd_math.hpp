@@ -56,6 +56,50 @@ __device__ __forceinline__ void decompose(const Geo& g, int c, int& i, int& j, i
 template <typename T> struct Fields { T* f[NF]; };
 template <typename T> struct CFields { const T* f[NF]; };
 
+// ---------------------------------------------------------------- roots and reciprocals
+
+// Square root, reciprocal square root and reciprocal used by the face solvers.
+// FP64: the hardware estimate refined by Newton-Raphson steps, which converge
+// quadratically, so the result lands within about one ulp of the correctly
+// rounded value at a third of the instruction count of the library forms.
+// Arguments are positive and normal (densities, pressures, squared speeds);
+// root_nr(0) = 0.  FP32: the single hardware instruction (about one ulp).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double h = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    double t = h * y;
+    double e = fma(-t, y, 0.5);
+    y = fma(y, e, y);
+    t = h * y;
+    e = fma(-t, y, 0.5);
+    return fma(y, e, y);
+}
+// coupled iteration on sqrt(x) and 1/(2 sqrt(x)), then one correction of the
+// root from its exact residual x - g^2
+__device__ __forceinline__ double root_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : 0.0;
+}
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float root_nr(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rcp_nr(float b) { return __builtin_amdgcn_rcpf(b); }
+
 // ---------------------------------------------------------------- local parabola (Sec. 2.1)
 
 template <typename T> struct Par { T qL, qR, dq, q6; };
@@ -116,7 +160,7 @@ __device__ __forceinline__ Par<T> parabola_finish(T qmm, T qm, T q0, T qp, T qpp
     bool need = !zero_eta && !sat_hi && !(ts <= EtaMargin<T>::lo * ds);
     T w = sat_hi ? T(1) : T(0);
     if (need) {
-        T eta = t / d;
+        T eta = t * rcp_nr(d);
         w = fmin(fmax(T(20) * (eta - T(0.05)), T(0)), T(1));
     }
     T fL = (T(1) - w) * nL + w * qLp;
@@ -213,41 +257,45 @@ __device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr,
 {
     const T eps = Eps<T>::v;
     // face averages (sqrt(rho) weights; cross weights for Bt)
-    T sl = sqrt(rl), sr = sqrt(rr);
-    T iw = T(1) / (sl + sr);
+    T sl = root_nr(rl), sr = root_nr(rr);
+    T iw = rcp_nr(sl + sr);
     T rho = (sl * rl + sr * rr) * iw;
     T p = (sl * pl + sr * pr) * iw;
     T bt1 = (sl * b1r + sr * b1l) * iw;
     T bt2 = (sl * b2r + sr * b2l) * iw;
 
-    // eigen-structure (Sec. 2.3, 2.4, eigenvector appendix)
-    T irho = T(1) / rho;
-    T c2 = gm * p * irho;
+    // eigen-structure (Sec. 2.3, 2.4, eigenvector appendix); every root and
+    // reciprocal of rho and gamma p derives from their two reciprocal roots
+    T rs = rsqrt_nr(rho);                // 1 / sqrt(rho)
+    T irho = rs * rs;
+    T srho = rho * rs;
+    T gp = gm * p;
+    T rg = rsqrt_nr(gp);                 // 1 / sqrt(gamma p) = 1 / (sqrt(rho) c)
+    T c2 = gp * irho;
     T ca2 = bn * bn * irho;
     T b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) * irho;
     T s = c2 + b2;
     T disc = fmax(s * s - T(4) * c2 * ca2, T(0));
-    T sd = sqrt(disc);
+    T sd = root_nr(disc);
     T cf2 = T(0.5) * (s + sd);
     T cs2 = fmax(T(0.5) * (s - sd), T(0));
-    T cc = sqrt(c2), ca = sqrt(ca2), cf = sqrt(cf2), cs = sqrt(cs2);
+    T cc = (gp * rg) * rs, ca = fabs(bn) * rs, cf = root_nr(cf2), cs = root_nr(cs2);
     const T r2i = T(0.70710678118654752440);
     T den = cf2 - cs2;
     T af = r2i, as = r2i;
     if (den > eps * s) {
-        T iden = T(1) / den;
-        af = sqrt(fmax(c2 - cs2, T(0)) * iden);
-        as = sqrt(fmax(cf2 - c2, T(0)) * iden);
+        T iden = rcp_nr(den);
+        af = root_nr(fmax(c2 - cs2, T(0)) * iden);
+        as = root_nr(fmax(cf2 - c2, T(0)) * iden);
     }
     T by = r2i, bz = r2i;
     T btsq = bt1 * bt1 + bt2 * bt2;
     if (btsq > eps * (bn * bn + btsq + gm * p)) {
-        T ibt = T(1) / sqrt(btsq);
+        T ibt = rsqrt_nr(btsq);
         by = bt1 * ibt;
         bz = bt2 * ibt;
     }
     T sg = bn >= T(0) ? T(1) : T(-1);
-    T srho = sqrt(rho);
 
     // parabola averages on the upwind side of each wave: waves +cf, +cs, +ca
     // read the left cell (right part, q(-nu t)), waves -cf, -cs, -ca the right
@@ -271,12 +319,10 @@ __device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr,
     }
 
     // characteristic amplitudes s_k = l_k . q_up(k)
-    T ic2 = T(1) / c2;
-    T isc = T(1) / (srho * cc);
-    T A = T(0.5) * ic2;                  // 1 / (2 c^2)
-    T Bc = T(0.5) * isc;                 // 1 / (2 sqrt(rho) c)
-    T Cc = A * irho;                     // 1 / (2 rho c^2)
-    T Dc = r2i / srho;                   // 1 / sqrt(2 rho)
+    T A = T(0.5) * (rho * (rg * rg));    // 1 / (2 c^2)
+    T Bc = T(0.5) * rg;                  // 1 / (2 sqrt(rho) c)
+    T Cc = T(0.5) * (rg * rg);           // 1 / (2 rho c^2)
+    T Dc = r2i * rs;                     // 1 / sqrt(2 rho)
     T afcf = af * cf, ascs = as * cs;
     auto vtb = [&](const T* q) { return by * q[1] + bz * q[2]; };
     auto btb = [&](const T* q) { return by * q[3] + bz * q[4]; };
@@ -291,9 +337,8 @@ __device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr,
 
     // face state q = sum_k r_k s_k
     T fdm = s0 - s1, fsm = s0 + s1, sdm = s2 - s3, ssm = s2 + s3, adm = s4 - s5, asm_ = s4 + s5;
-    T src = srho * cc;
+    T src = gp * rg;                     // sqrt(rho) c = sqrt(gamma p)
     T sr2 = r2i * srho;
-    T gp = gm * p;
     T Vn = afcf * fdm + ascs * sdm;
     T Vt1 = sg * by * (-ascs * fdm + afcf * sdm) - bz * sg * r2i * asm_;
     T Vt2 = sg * bz * (-ascs * fdm + afcf * sdm) + by * sg * r2i * asm_;
