@@ -358,6 +358,9 @@ void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, con
     }
 }
 
+// z cells per thread in the NONADV update march
+constexpr int NONADV_UPDATE_SEG = 32;
+
 template <typename T, class Emit>
 void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg,
                           bool first)
@@ -386,7 +389,9 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
     ua.a = a;
     ua.rk = rk;
     ua.dbg = dbg;
-    e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, b->nblocks, 0, ua);
+    ua.seg = b->g.nz < NONADV_UPDATE_SEG ? b->g.nz : NONADV_UPDATE_SEG;
+    long long threads = (long long)b->g.nx * b->g.ny * ((b->g.nz + ua.seg - 1) / ua.seg);
+    e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, (int)((threads + NTH - 1) / NTH), 0, ua);
 }
 
 template <typename T, int D, class Emit>
@@ -410,7 +415,7 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     emit_adv_face<T, 1>(b, e, in, a);
     // z faces marched together with the update of every cell
     constexpr int ADV_SEG = 32;
-    typename BAdvZUpdate<T>::Args ua;
+    AdvZArgs<T> ua;
     ua.g = b->g;
     ua.U = cview(in);
     ua.S = cview(S);
@@ -422,7 +427,9 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     ua.dbg = dbg;
     ua.seg = b->g.nz < ADV_SEG ? b->g.nz : ADV_SEG;
     long long threads = (long long)b->g.nx * b->g.ny * ((b->g.nz + ua.seg - 1) / ua.seg);
-    e.template launch<BAdvZUpdate<T>>(MHD_K_ADV_UPDATE, (int)((threads + NTH - 1) / NTH), 0, ua);
+    const int blocks = (int)((threads + NTH - 1) / NTH);
+    e.template launch<BAdvZUpdate<T, 0, 4>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // rho, m
+    e.template launch<BAdvZUpdate<T, 4, 3>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2
 }
 
 // NONADV stage: the M and B groups each rotate through their three slots

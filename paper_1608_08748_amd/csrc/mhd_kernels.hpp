@@ -169,10 +169,12 @@ struct BFacePair {
     }
 };
 
-// NONADV faces along x with whole x rows per block: each thread computes the
-// parabolas of its own cell once; the left neighbour's side comes from LDS
-// (periodic wrap inside the row), so no parabola is computed twice.  Dynamic
-// LDS: NT * 18 values.
+// NONADV faces along x with whole x rows per block: each thread owns one cell
+// and computes, once each, its limited slopes, the interface values at its
+// lower face and its parabolas (Sec. 2.1); neighbours' slopes, interface
+// values and parabola sides come through LDS (periodic wrap inside the row).
+// Dynamic LDS: 18 x NT values, value k of thread t at k * NT + t, reused by
+// the three exchanges.
 template <typename T, int MAXT>
 struct BFaceXRows {
     static constexpr int NT = MAXT;
@@ -192,30 +194,63 @@ struct BFaceXRows {
         int row = blk * A.rpb + r;
         bool act = r < A.rpb && row < g.ny * g.nz;
         int rowbase = row * nx;
-        Side<T> R;
+        int il = i == 0 ? nx - 1 : i - 1;
+        int tl = r * nx + il;                          // thread of the left cell
+        int tr = r * nx + (i + 1 == nx ? 0 : i + 1);   // thread of the right cell
+        // q1, q2: the own and left cells' values, kept across the exchanges;
+        // the outer stencil values are read again where they are needed
+        T q1[6], q2[6], dm[6], fl[6];
+        const int im2 = wrapc(i - 2, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
+        // slopes of the own cell
         if (act) {
-            int im2 = wrapc(i - 2, nx), im1 = wrapc(i - 1, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
-            T* mine = sm + (size_t)(r * nx + i) * 18;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                const T* q = W + (size_t)V::f[v] * N + rowbase;
-                Par<T> P = parabola(q[im2], q[im1], q[i], q[ip1], q[ip2]);
-                side_right(P, R, v);
-                mine[3 * v + 0] = P.qR;
-                mine[3 * v + 1] = P.dq;
-                mine[3 * v + 2] = P.q6;
+                const T* qv = W + (size_t)V::f[v] * N + rowbase;
+                q1[v] = qv[il];
+                q2[v] = qv[i];
+                dm[v] = limited_slope(q1[v], q2[v], qv[ip1]);
+                sm[v * NT + tid] = dm[v];
             }
         }
         __syncthreads();
+        // interface value at the lower face, from the left cell's slope
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < 6; v++) {
+                fl[v] = interface_value(q1[v], q2[v], sm[v * NT + tl], dm[v]);
+                sm[(6 + v) * NT + tid] = fl[v];
+            }
+        }
+        __syncthreads();
+        // parabolas of the own cell; the upper interface value is the right
+        // cell's lower one
+        Side<T> R;
+        T pub[18];
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < 6; v++) {
+                const T* qv = W + (size_t)V::f[v] * N + rowbase;
+                T fr = sm[(6 + v) * NT + tr];
+                Par<T> P = parabola_finish(qv[im2], q1[v], q2[v], qv[ip1], qv[ip2], fl[v], fr, dm[v]);
+                side_right(P, R, v);
+                pub[3 * v + 0] = P.qR;
+                pub[3 * v + 1] = P.dq;
+                pub[3 * v + 2] = P.q6;
+            }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < 18; k++) sm[k * NT + tid] = pub[k];
+        }
+        __syncthreads();
         if (!act) return;
-        int il = i == 0 ? nx - 1 : i - 1;
-        const T* left = sm + (size_t)(r * nx + il) * 18;
         Side<T> L;
 #pragma unroll
         for (int v = 0; v < 6; v++) {
-            L.e[v] = left[3 * v + 0];
-            L.dq[v] = left[3 * v + 1];
-            L.q6[v] = left[3 * v + 2];
+            L.e[v] = sm[(3 * v + 0) * NT + tl];
+            L.dq[v] = sm[(3 * v + 1) * NT + tl];
+            L.q6[v] = sm[(3 * v + 2) * NT + tl];
         }
         int c = rowbase + i, cl = rowbase + il;
         T out[7];
@@ -319,7 +354,10 @@ struct BFaceMarch {
 
 // NONADV update: flux differences, p dV work, face-field update from edge
 // fields (Sec. 2.5), Runge-Kutta combination (Sec. 2.2).  dbg != 0 writes
-// tau R(U) instead of the combination.
+// tau R(U) instead of the combination.  Each thread marches along z over a
+// segment of `seg` cells; the z-face values at the upper face of cell k and
+// the two edge fields on its upper z edges are the lower ones of cell k+1, so
+// they are carried instead of read or formed again (same arithmetic).
 template <typename T>
 struct BNonadvUpdate {
     static constexpr int NT = NTH;
@@ -334,37 +372,30 @@ struct BNonadvUpdate {
         StepArgs a;
         RK rk;
         int dbg;
+        int seg;
     };
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
-        int c = blk * NT + tid;
-        if (c >= g.n) return;
-        int i, j, k;
-        decompose(g, c, i, j, k);
+        const int seg = A.seg;
+        const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy;
+        const int nseg = (nz + seg - 1) / seg;
+        int t = blk * NT + tid;
+        int i = t % nx;
+        int rest = t / nx;
+        int j = rest % ny;
+        int sgi = rest / ny;
+        if (sgi >= nseg) return;
+        const int k0 = sgi * seg;
+        const int k1 = min(k0 + seg, nz);
         const size_t N = (size_t)g.n;
         const T dtdx = T(step_dt(A.a) / A.a.h);
         const T* Fx = A.Fx;
         const T* Fy = A.Fy;
         const T* Fz = A.Fz;
-        int xp = nbr<0>(g, c, i, j, k, 1), xm = nbr<0>(g, c, i, j, k, -1);
-        int yp = nbr<1>(g, c, i, j, k, 1), ym = nbr<1>(g, c, i, j, k, -1);
-        int zp = nbr<2>(g, c, i, j, k, 1), zm = nbr<2>(g, c, i, j, k, -1);
-        const T* Fd[3] = { Fx, Fy, Fz };
-        int up[3] = { xp, yp, zp };
-        T dF[3][5];
-#pragma unroll
-        for (int d = 0; d < 3; d++)
-#pragma unroll
-            for (int v = 0; v < 5; v++) dF[d][v] = Fd[d][v * N + up[d]] - Fd[d][v * N + c];
-        T inc[NF];
-        // momentum component a takes slot (a - d) mod 3 from direction d
-        inc[MX] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
-        inc[MY] = -dtdx * ((dF[0][1] + dF[1][0]) + dF[2][2]);
-        inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
-        inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
-        T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
-        inc[EI] = -T(A.a.gamma - 1.0) * A.U.f[EI][c] * dtdx * divv;
+        // periodic neighbour offsets in the x-y plane
+        const int dxp = (i + 1 == nx ? 0 : i + 1) - i, dxm = (i == 0 ? nx - 1 : i - 1) - i;
+        const int dyp = ((j + 1 == ny ? 0 : j + 1) - j) * nx, dym = ((j == 0 ? ny - 1 : j - 1) - j) * nx;
 
         // edge fields (electric-field appendix): Ex at (i, j-1/2, k-1/2) from
         // z faces at j-1, j and y faces at k, k-1; Ey at (i-1/2, j, k-1/2) from
@@ -379,40 +410,71 @@ struct BNonadvUpdate {
         auto Ex = [&](int cc, int cym, int czm) { return T(0.25) * (((ezx[cym] + ezx[cc]) + eyx[cc]) + eyx[czm]); };
         auto Ey = [&](int cc, int cxm, int czm) { return T(0.25) * (((ezy[cxm] + ezy[cc]) + exy[czm]) + exy[cc]); };
         auto Ez = [&](int cc, int cym, int cxm) { return T(0.25) * (((exz[cym] + exz[cc]) + eyz[cxm]) + eyz[cc]); };
-        int ip, jp, kp;
-        T Ex_c = Ex(c, ym, zm);
-        decompose(g, yp, ip, jp, kp);
-        T Ex_yp = Ex(yp, c, nbr<2>(g, yp, ip, jp, kp, -1));
-        decompose(g, zp, ip, jp, kp);
-        T Ex_zp = Ex(zp, nbr<1>(g, zp, ip, jp, kp, -1), c);
-        T Ey_c = Ey(c, xm, zm);
-        decompose(g, xp, ip, jp, kp);
-        T Ey_xp = Ey(xp, c, nbr<2>(g, xp, ip, jp, kp, -1));
-        decompose(g, zp, ip, jp, kp);
-        T Ey_zp = Ey(zp, nbr<0>(g, zp, ip, jp, kp, -1), c);
-        T Ez_c = Ez(c, ym, xm);
-        decompose(g, xp, ip, jp, kp);
-        T Ez_xp = Ez(xp, nbr<1>(g, xp, ip, jp, kp, -1), c);
-        decompose(g, yp, ip, jp, kp);
-        T Ez_yp = Ez(yp, c, nbr<0>(g, yp, ip, jp, kp, -1));
-        inc[BX] = -dtdx * (Ez_yp - Ez_c) + dtdx * (Ey_zp - Ey_c);
-        inc[BY] = -dtdx * (Ex_zp - Ex_c) + dtdx * (Ez_xp - Ez_c);
-        inc[BZ] = -dtdx * (Ey_xp - Ey_c) + dtdx * (Ex_yp - Ex_c);
 
-        const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
-        if (A.dbg) {
+        // carried: z-face values at the lower face of the current cell and the
+        // Ex, Ey on its lower z edges
+        T fzc[5];
+        T Ex_c, Ey_c;
+        {
+            int c = i + nx * j + nxy * k0;
+            int zm = c + ((k0 == 0 ? nz - 1 : k0 - 1) - k0) * nxy;
 #pragma unroll
-            for (int q = 0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
-            A.O.f[RHO][c] = T(0);
-            A.O.f[H2][c] = T(0);
-            return;
+            for (int v = 0; v < 5; v++) fzc[v] = Fz[v * N + c];
+            Ex_c = Ex(c, c + dym, zm);
+            Ey_c = Ey(c, c + dxm, zm);
         }
         const T ra = T(A.rk.a), rb = T(A.rk.b);
+        const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
+        for (int k = k0; k < k1; k++) {
+            const int c = i + nx * j + nxy * k;
+            const int dzp = ((k + 1 == nz ? 0 : k + 1) - k) * nxy;
+            const int dzm = ((k == 0 ? nz - 1 : k - 1) - k) * nxy;
+            const int xp = c + dxp, xm = c + dxm, yp = c + dyp, ym = c + dym, zp = c + dzp;
+            T dF[3][5], fzp[5];
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            int f = upd[q];
-            T u = A.U.f[f][c];
-            A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc[f];
+            for (int v = 0; v < 5; v++) {
+                dF[0][v] = Fx[v * N + xp] - Fx[v * N + c];
+                dF[1][v] = Fy[v * N + yp] - Fy[v * N + c];
+                fzp[v] = Fz[v * N + zp];
+                dF[2][v] = fzp[v] - fzc[v];
+            }
+            T inc[NF];
+            // momentum component a takes slot (a - d) mod 3 from direction d
+            inc[MX] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
+            inc[MY] = -dtdx * ((dF[0][1] + dF[1][0]) + dF[2][2]);
+            inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
+            inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
+            T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
+            inc[EI] = -T(A.a.gamma - 1.0) * A.U.f[EI][c] * dtdx * divv;
+
+            T Ex_yp = Ex(yp, c, yp + dzm);
+            T Ex_zp = Ex(zp, zp + dym, c);
+            T Ey_xp = Ey(xp, c, xp + dzm);
+            T Ey_zp = Ey(zp, zp + dxm, c);
+            T Ez_c = Ez(c, ym, xm);
+            T Ez_xp = Ez(xp, xp + dym, c);
+            T Ez_yp = Ez(yp, c, yp + dxm);
+            inc[BX] = -dtdx * (Ez_yp - Ez_c) + dtdx * (Ey_zp - Ey_c);
+            inc[BY] = -dtdx * (Ex_zp - Ex_c) + dtdx * (Ez_xp - Ez_c);
+            inc[BZ] = -dtdx * (Ey_xp - Ey_c) + dtdx * (Ex_yp - Ex_c);
+
+            if (A.dbg) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
+                A.O.f[RHO][c] = T(0);
+                A.O.f[H2][c] = T(0);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    int f = upd[q];
+                    T u = A.U.f[f][c];
+                    A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc[f];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 5; v++) fzc[v] = fzp[v];
+            Ex_c = Ex_zp;
+            Ey_c = Ey_zp;
         }
     }
 };
@@ -462,43 +524,47 @@ struct BAdvFace {
     }
 };
 
-// ADV z faces fused with the ADV update: each thread marches along z over a
-// segment of cells with a sliding 6-cell window of the 7 advected fields, so
+// ADV z faces fused with the ADV update, for the advected fields Q0 ..
+// Q0+NQ-1 of the order rho, mx, my, mz, E, e, h2: each thread marches along z
+// over a segment of cells with a sliding 6-cell window of those fields, so
 // the flux at the upper z face of cell k is the lower one of cell k+1, and the
 // update reads the x and y fluxes written by the x/y face kernels.  Same
-// arithmetic as BAdvFace<T,2> followed by BAdvUpdate.
+// arithmetic as the x/y face kernels followed by a plain update.  The fields
+// are split over several launches so that a thread holds a small window and
+// more waves fit on a SIMD; every launch reads rho and mz of the two cells at
+// each face for the face velocity.
 template <typename T>
+struct AdvZArgs {
+    Geo g;
+    CFields<T> U, S;
+    Fields<T> O;
+    const T* Fx;
+    const T* Fy;
+    StepArgs a;
+    RK rk;
+    int dbg;
+    int seg;
+};
+
+template <typename T, int Q0, int NQ>
 struct BAdvZUpdate {
     static constexpr int NT = NTH;
     static constexpr bool XCD = false;
-    struct Args {
-        Geo g;
-        CFields<T> U, S;
-        Fields<T> O;
-        const T* Fx;
-        const T* Fy;
-        StepArgs a;
-        RK rk;
-        int dbg;
-        int seg;
-    };
-    // flux of the 7 fields through the face between window cells m and m+1
-    // (window cell m is z index k-2+m)
-    static __device__ __forceinline__ void zflux(const T w[7][6], int m, T ydx, T out[7])
+    using Args = AdvZArgs<T>;
+    // fluxes of the group's fields through the face between window slots 2
+    // and 3 (cells k and k+1 of a window that starts at k-2), face velocity vf
+    static __device__ __forceinline__ void zflux(const T w[NQ][6], T vf, T ydx, T out[NQ])
     {
-        T rl = w[0][m], rr = w[0][m + 1];
-        T rsl = rsqrt_nr(rl), rsr = rsqrt_nr(rr);
-        T vf = (w[3][m] * rsl + w[3][m + 1] * rsr) * rcp_nr(rl * rsl + rr * rsr);
         bool upw = vf >= T(0);
         T y = upw ? ydx * vf : ydx * (-vf);
 #pragma unroll
-        for (int q = 0; q < 7; q++) {
-            // upwind cell m (window m-2..m+2) or m+1 (window m-1..m+3)
-            T q0 = upw ? w[q][m - 2] : w[q][m - 1];
-            T q1 = upw ? w[q][m - 1] : w[q][m];
-            T q2 = upw ? w[q][m] : w[q][m + 1];
-            T q3 = upw ? w[q][m + 1] : w[q][m + 2];
-            T q4 = upw ? w[q][m + 2] : w[q][m + 3];
+        for (int q = 0; q < NQ; q++) {
+            // upwind cell: slot 2 (stencil slots 0..4) or slot 3 (slots 1..5)
+            T q0 = upw ? w[q][0] : w[q][1];
+            T q1 = upw ? w[q][1] : w[q][2];
+            T q2 = upw ? w[q][2] : w[q][3];
+            T q3 = upw ? w[q][3] : w[q][4];
+            T q4 = upw ? w[q][4] : w[q][5];
             Par<T> P = parabola(q0, q1, q2, q3, q4);
             T qup = upw ? avg_right(P, y) : avg_left(P, y);
             out[q] = vf * qup;
@@ -528,40 +594,57 @@ struct BAdvZUpdate {
         int ip = i + 1 == g.nx ? 0 : i + 1;
         int jp = j + 1 == g.ny ? 0 : j + 1;
 
-        // window cells z = x0-3 .. x0+2 (slots 0..5): the first face is x0-1/2
-        T w[7][6];
+        // window cells z = x0-3 .. x0+2 (slots 0..5): the first face is
+        // x0-1/2.  vr, vm: rho and mz of slots 2 and 3, for the face velocity.
+        T w[NQ][6];
+        T vr[2], vm[2];
 #pragma unroll
         for (int m = 0; m < 6; m++) {
             int cc = base + wrapc(x0 - 3 + m, nd) * stride;
 #pragma unroll
-            for (int q = 0; q < 7; q++) w[q][m] = A.U.f[fld[q]][cc];
+            for (int q = 0; q < NQ; q++) w[q][m] = A.U.f[fld[Q0 + q]][cc];
+            if (m == 2 || m == 3) {   // constant after unrolling
+                vr[m - 2] = A.U.f[RHO][cc];
+                vm[m - 2] = A.U.f[MZ][cc];
+            }
         }
-        // face between window slots 2 and 3 = cells x0-1 and x0; parabola
-        // stencils use slots 0..4 or 1..5
-        T Flo[7];
-        zflux(w, 2, ydx, Flo);
+        auto velocity = [&]() {
+            // sqrt(rho)-weighted face velocity; sqrt(rho) v = m / sqrt(rho)
+            T rsl = rsqrt_nr(vr[0]), rsr = rsqrt_nr(vr[1]);
+            return (vm[0] * rsl + vm[1] * rsr) * rcp_nr(vr[0] * rsl + vr[1] * rsr);
+        };
+        T Flo[NQ];
+        zflux(w, velocity(), ydx, Flo);
         for (int x = x0; x < x1; x++) {
             // slide: window slots 0..5 = cells x-2 .. x+3
             int cn = base + wrapc(x + 3, nd) * stride;
 #pragma unroll
-            for (int q = 0; q < 7; q++) {
+            for (int q = 0; q < NQ; q++) {
 #pragma unroll
                 for (int m = 0; m < 5; m++) w[q][m] = w[q][m + 1];
-                w[q][5] = A.U.f[fld[q]][cn];
+                w[q][5] = A.U.f[fld[Q0 + q]][cn];
+            }
+            {
+                int c1 = base + wrapc(x + 1, nd) * stride;
+                vr[0] = vr[1];
+                vm[0] = vm[1];
+                vr[1] = A.U.f[RHO][c1];
+                vm[1] = A.U.f[MZ][c1];
             }
             // upper face of cell x: between slots 2 (cell x) and 3 (cell x+1)
-            T Fup[7];
-            zflux(w, 2, ydx, Fup);
+            T Fup[NQ];
+            zflux(w, velocity(), ydx, Fup);
             int c = base + x * stride;
             int cxp = c - i + ip;
             int cyp = c + (jp - j) * g.nx;
 #pragma unroll
-            for (int q = 0; q < 7; q++) {
-                T dx = A.Fx[q * N + cxp] - A.Fx[q * N + c];
-                T dy = A.Fy[q * N + cyp] - A.Fy[q * N + c];
+            for (int q = 0; q < NQ; q++) {
+                const size_t o = (size_t)(Q0 + q) * N;
+                T dx = A.Fx[o + cxp] - A.Fx[o + c];
+                T dy = A.Fy[o + cyp] - A.Fy[o + c];
                 T dz = Fup[q] - Flo[q];
                 T inc = -dtdx * ((dx + dy) + dz);
-                int f = fld[q];
+                int f = fld[Q0 + q];
                 if (A.dbg) {
                     A.O.f[f][c] = inc;
                 } else {
@@ -570,60 +653,11 @@ struct BAdvZUpdate {
                 }
                 Flo[q] = Fup[q];
             }
-            if (A.dbg) {
+            if (Q0 == 0 && A.dbg) {
                 A.O.f[BX][c] = T(0);
                 A.O.f[BY][c] = T(0);
                 A.O.f[BZ][c] = T(0);
             }
-        }
-    }
-};
-
-template <typename T>
-struct BAdvUpdate {
-    static constexpr int NT = NTH;
-    static constexpr bool XCD = false;
-    struct Args {
-        Geo g;
-        CFields<T> U, S;
-        Fields<T> O;
-        const T* Fx;
-        const T* Fy;
-        const T* Fz;
-        StepArgs a;
-        RK rk;
-        int dbg;
-    };
-    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
-    {
-        const Geo& g = A.g;
-        int c = blk * NT + tid;
-        if (c >= g.n) return;
-        int i, j, k;
-        decompose(g, c, i, j, k);
-        const size_t N = (size_t)g.n;
-        const T dtdx = T(step_dt(A.a) / A.a.h);
-        int xp = nbr<0>(g, c, i, j, k, 1), yp = nbr<1>(g, c, i, j, k, 1), zp = nbr<2>(g, c, i, j, k, 1);
-        const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
-        const T ra = T(A.rk.a), rb = T(A.rk.b);
-#pragma unroll
-        for (int q = 0; q < 7; q++) {
-            T dx = A.Fx[q * N + xp] - A.Fx[q * N + c];
-            T dy = A.Fy[q * N + yp] - A.Fy[q * N + c];
-            T dz = A.Fz[q * N + zp] - A.Fz[q * N + c];
-            T inc = -dtdx * ((dx + dy) + dz);
-            int f = fld[q];
-            if (A.dbg) {
-                A.O.f[f][c] = inc;
-            } else {
-                T u = A.U.f[f][c];
-                A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc;
-            }
-        }
-        if (A.dbg) {
-            A.O.f[BX][c] = T(0);
-            A.O.f[BY][c] = T(0);
-            A.O.f[BZ][c] = T(0);
         }
     }
 };
