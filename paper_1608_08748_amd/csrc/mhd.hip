@@ -333,7 +333,7 @@ void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, con
             e.template launch<BFaceXRows<T, 256>>(MHD_K_NONADV_FACE, blocks, 256 * 18 * sizeof(T), fa);
         else if (g.nx <= 512)
             e.template launch<BFaceXRows<T, 512>>(MHD_K_NONADV_FACE, blocks, 512 * 18 * sizeof(T), fa);
-        else
+        else if constexpr (sizeof(T) == 4)   // 1024-thread rows only in FP32 (register budget)
             e.template launch<BFaceXRows<T, 1024>>(MHD_K_NONADV_FACE, blocks, 1024 * 18 * sizeof(T), fa);
     } else {
         fa.rpb = 0;

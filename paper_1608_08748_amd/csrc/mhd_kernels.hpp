@@ -197,18 +197,30 @@ struct BFaceXRows {
         int il = i == 0 ? nx - 1 : i - 1;
         int tl = r * nx + il;                          // thread of the left cell
         int tr = r * nx + (i + 1 == nx ? 0 : i + 1);   // thread of the right cell
-        // q1, q2: the own and left cells' values, kept across the exchanges;
-        // the outer stencil values are read again where they are needed
-        T q1[6], q2[6], dm[6], fl[6];
+        // every global value the thread needs is read before the first
+        // exchange: the 5-cell line of each variable and the two cells'
+        // densities and face normal field (the pressures and transverse
+        // fields of the face solve are line values q1, q2)
+        T q0[6], q1[6], q2[6], q3[6], q4[6], dm[6], fl[6];
+        T rl = T(0), rr = T(0), bn = T(0);
         const int im2 = wrapc(i - 2, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
         // slopes of the own cell
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
                 const T* qv = W + (size_t)V::f[v] * N + rowbase;
+                q0[v] = qv[im2];
                 q1[v] = qv[il];
                 q2[v] = qv[i];
-                dm[v] = limited_slope(q1[v], q2[v], qv[ip1]);
+                q3[v] = qv[ip1];
+                q4[v] = qv[ip2];
+            }
+            rl = W[rowbase + il];
+            rr = W[rowbase + i];
+            bn = A.bface[rowbase + i];
+#pragma unroll
+            for (int v = 0; v < 6; v++) {
+                dm[v] = limited_slope(q1[v], q2[v], q3[v]);
                 sm[v * NT + tid] = dm[v];
             }
         }
@@ -229,9 +241,8 @@ struct BFaceXRows {
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                const T* qv = W + (size_t)V::f[v] * N + rowbase;
                 T fr = sm[(6 + v) * NT + tr];
-                Par<T> P = parabola_finish(qv[im2], q1[v], q2[v], qv[ip1], qv[ip2], fl[v], fr, dm[v]);
+                Par<T> P = parabola_finish(q0[v], q1[v], q2[v], q3[v], q4[v], fl[v], fr, dm[v]);
                 side_right(P, R, v);
                 pub[3 * v + 0] = P.qR;
                 pub[3 * v + 1] = P.dq;
@@ -252,12 +263,11 @@ struct BFaceXRows {
             L.dq[v] = sm[(3 * v + 1) * NT + tl];
             L.q6[v] = sm[(3 * v + 2) * NT + tl];
         }
-        int c = rowbase + i, cl = rowbase + il;
         T out[7];
-        face_solve(W[cl], W[7 * N + cl], W[(size_t)V::f[3] * N + cl], W[(size_t)V::f[4] * N + cl], W[c],
-                   W[7 * N + c], W[(size_t)V::f[3] * N + c], W[(size_t)V::f[4] * N + c], A.bface[c], L, R,
-                   T(A.a.gamma), T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
-        store_face(A.F, N, c, out);
+        // parabola variables 3, 4, 5 are Bt1, Bt2, p
+        face_solve(rl, q1[5], q1[3], q1[4], rr, q2[5], q2[3], q2[4], bn, L, R, T(A.a.gamma),
+                   T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+        store_face(A.F, N, rowbase + i, out);
     }
 };
 
