@@ -358,8 +358,26 @@ void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, con
     }
 }
 
-// z cells per thread in the NONADV update march
-constexpr int NONADV_UPDATE_SEG = 32;
+// z cells per thread in the z-marching update kernels
+constexpr int ZMARCH_SEG = 32;
+
+// tiles of the z-marching update kernels: 64 x cells (a wave) by NTH / 64
+// rows, narrower for thin boxes
+ZTile ztile_of(const Geo& g)
+{
+    ZTile z;
+    z.tx = g.nx < 64 ? g.nx : 64;
+    z.ty = NTH / z.tx;
+    z.ntx = (g.nx + z.tx - 1) / z.tx;
+    z.nty = (g.ny + z.ty - 1) / z.ty;
+    z.seg = g.nz < ZMARCH_SEG ? g.nz : ZMARCH_SEG;
+    return z;
+}
+
+int ztile_blocks(const Geo& g, const ZTile& z)
+{
+    return z.ntx * z.nty * ((g.nz + z.seg - 1) / z.seg);
+}
 
 template <typename T, class Emit>
 void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg,
@@ -389,9 +407,8 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
     ua.a = a;
     ua.rk = rk;
     ua.dbg = dbg;
-    ua.seg = b->g.nz < NONADV_UPDATE_SEG ? b->g.nz : NONADV_UPDATE_SEG;
-    long long threads = (long long)b->g.nx * b->g.ny * ((b->g.nz + ua.seg - 1) / ua.seg);
-    e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, (int)((threads + NTH - 1) / NTH), 0, ua);
+    ua.zt = ztile_of(b->g);
+    e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
 }
 
 template <typename T, int D, class Emit>
@@ -414,7 +431,6 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     emit_adv_face<T, 0>(b, e, in, a);
     emit_adv_face<T, 1>(b, e, in, a);
     // z faces marched together with the update of every cell
-    constexpr int ADV_SEG = 32;
     AdvZArgs<T> ua;
     ua.g = b->g;
     ua.U = cview(in);
@@ -425,9 +441,8 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     ua.a = a;
     ua.rk = rk;
     ua.dbg = dbg;
-    ua.seg = b->g.nz < ADV_SEG ? b->g.nz : ADV_SEG;
-    long long threads = (long long)b->g.nx * b->g.ny * ((b->g.nz + ua.seg - 1) / ua.seg);
-    const int blocks = (int)((threads + NTH - 1) / NTH);
+    ua.zt = ztile_of(b->g);
+    const int blocks = ztile_blocks(b->g, ua.zt);
     e.template launch<BAdvZUpdate<T, 0, 4>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // rho, m
     e.template launch<BAdvZUpdate<T, 4, 3>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2
 }

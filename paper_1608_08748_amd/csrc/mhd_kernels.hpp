@@ -46,6 +46,32 @@ __device__ __forceinline__ int logical_block()
     return Body::XCD ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
 }
 
+// Cell column (i, j) and z segment of a thread of a z-marching kernel: blocks
+// cover tx x ty tiles of the x-y plane, x fastest, then the segments, so the
+// y-neighbour rows a thread reads are mostly rows of its own block.  False
+// for the idle threads of ragged tiles.
+struct ZTile {
+    int tx, ty;     // tile shape; tx * ty <= block size
+    int ntx, nty;   // tiles per plane along x and y
+    int seg;        // z cells per thread
+};
+
+__device__ __forceinline__ bool ztile_cell(const Geo& g, const ZTile& z, int blk, int tid, int& i, int& j, int& k0,
+                                           int& k1)
+{
+    int ly = tid / z.tx;
+    int lx = tid - ly * z.tx;
+    int bx = blk % z.ntx;
+    int rest = blk / z.ntx;
+    int by = rest % z.nty;
+    int sg = rest / z.nty;
+    i = bx * z.tx + lx;
+    j = by * z.ty + ly;
+    k0 = sg * z.seg;
+    k1 = min(k0 + z.seg, g.nz);
+    return ly < z.ty && i < g.nx && j < g.ny && k0 < g.nz;
+}
+
 template <class Body>
 __global__ __launch_bounds__(Body::NT) void k_one(typename Body::Args a)
 {
@@ -365,7 +391,7 @@ struct BFaceMarch {
 // NONADV update: flux differences, p dV work, face-field update from edge
 // fields (Sec. 2.5), Runge-Kutta combination (Sec. 2.2).  dbg != 0 writes
 // tau R(U) instead of the combination.  Each thread marches along z over a
-// segment of `seg` cells; the z-face values at the upper face of cell k and
+// segment of cells (ZTile); the z-face values at the upper face of cell k and
 // the two edge fields on its upper z edges are the lower ones of cell k+1, so
 // they are carried instead of read or formed again (same arithmetic).
 template <typename T>
@@ -382,22 +408,14 @@ struct BNonadvUpdate {
         StepArgs a;
         RK rk;
         int dbg;
-        int seg;
+        ZTile zt;
     };
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
-        const int seg = A.seg;
         const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy;
-        const int nseg = (nz + seg - 1) / seg;
-        int t = blk * NT + tid;
-        int i = t % nx;
-        int rest = t / nx;
-        int j = rest % ny;
-        int sgi = rest / ny;
-        if (sgi >= nseg) return;
-        const int k0 = sgi * seg;
-        const int k1 = min(k0 + seg, nz);
+        int i, j, k0, k1;
+        if (!ztile_cell(g, A.zt, blk, tid, i, j, k0, k1)) return;
         const size_t N = (size_t)g.n;
         const T dtdx = T(step_dt(A.a) / A.a.h);
         const T* Fx = A.Fx;
@@ -553,7 +571,7 @@ struct AdvZArgs {
     StepArgs a;
     RK rk;
     int dbg;
-    int seg;
+    ZTile zt;
 };
 
 template <typename T, int Q0, int NQ>
@@ -583,20 +601,12 @@ struct BAdvZUpdate {
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
-        const int seg = A.seg;
         const int nd = g.nz;
-        const int nseg = (nd + seg - 1) / seg;
-        int t = blk * NT + tid;
-        int i = t % g.nx;
-        int rest = t / g.nx;
-        int j = rest % g.ny;
-        int sgi = rest / g.ny;
-        if (sgi >= nseg) return;
+        int i, j, x0, x1;
+        if (!ztile_cell(g, A.zt, blk, tid, i, j, x0, x1)) return;
         const size_t N = (size_t)g.n;
         const int base = i + g.nx * j;
         const int stride = g.nxy;
-        const int x0 = sgi * seg;
-        const int x1 = min(x0 + seg, nd);
         const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
         const T dtdx = T(step_dt(A.a) / A.a.h);
         const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
