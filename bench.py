@@ -97,7 +97,10 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 # the kernel sources at the time the counters were taken; FETCH_SIZE is scaled
 # by 2 and WRITE_SIZE by 1, the factors that make a 1 GiB device copy read and
 # write 1 GiB
-TRAFFIC = {}
+TRAFFIC = {
+    # average of the x-row, y-march and z-march face kernels, bytes per launch
+    ("c2", 8, "nonadv_face"): ("25489c8f72b1aa95", 2105763840),
+}
 
 
 def _kernel_source_hash():
