@@ -84,11 +84,14 @@ def _timed_run(box, steps, dts=None):
     return time.perf_counter() - t0, used
 
 
-# algorithmic floating-point operations per face of the NONADV face kernels
-# (six parabolas of one cell, about 93 each, plus the face solve: averages,
-# eigen-structure, 36 parabola averages, characteristic amplitudes, projector
-# sum and fluxes, about 366; a square root or a division counts as one)
-ALG_FLOPS = {"nonadv_face": 6 * 93 + 366}
+# algorithmic floating-point operations per face of the NONADV face kernels,
+# counted on the formulas with every add, subtract, multiply, divide, square
+# root, min, max and comparison as one: per parabola variable (six) one
+# limited slope (11), one interface value (5) and the Steps 2-5 finish (70);
+# then the face solve: averaged state 20, eigen-structure 55, the 32 parabola
+# averages the waves read 140, characteristic amplitudes 97, projector sum 49,
+# fluxes and edge-field terms 24
+ALG_FLOPS = {"nonadv_face": 6 * (11 + 5 + 70) + (20 + 55 + 140 + 97 + 49 + 24)}
 # published MI355X vector peaks (TFLOP/s) and HBM peak
 VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 
