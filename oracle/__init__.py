@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("theta", ctypes.c_double),
-        ("chemistry", ctypes.c_int),
+        ("chemistry", ctypes.c_int), ("cooling", ctypes.c_int),
         ("n_unit", ctypes.c_double), ("T_unit", ctypes.c_double), ("t_unit", ctypes.c_double),
     ]
 
@@ -73,6 +73,12 @@ def lib():
             ("orc_k3", [ctypes.c_double], ctypes.c_double),
             ("orc_k4", [], ctypes.c_double),
             ("orc_chem_cell", [P] + [ctypes.c_double] * 4 + [_D], ctypes.c_double),
+            ("orc_ncrit", [ctypes.c_double], ctypes.c_double),
+            ("orc_lh2", [ctypes.c_double], ctypes.c_double),
+            ("orc_ll2", [ctypes.c_double] * 3, ctypes.c_double),
+            ("orc_ln_ll3", [ctypes.c_double] * 2, ctypes.c_double),
+            ("orc_heat_cool", [P] + [ctypes.c_double] * 3 + [_D], ctypes.c_double),
+            ("orc_cooling", [P, _D, ctypes.c_double], None),
             ("orc_clamp_h2", [P, _D], None),
             ("orc_chemistry", [P, _D, ctypes.c_double], None),
             ("orc_regularise", [P, _D], None),
@@ -102,10 +108,10 @@ def default_units():
     return 5.0, T_u, 256.0 * pc / v_u
 
 
-def make_params(shape, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None):
+def make_params(shape, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None, cooling=False):
     nz, ny, nx = shape
     nu, Tu, tu = units if units is not None else default_units()
-    return Params(nx, ny, nz, gamma, cfl, theta, 1 if chemistry else 0, nu, Tu, tu)
+    return Params(nx, ny, nz, gamma, cfl, theta, 1 if chemistry else 0, 1 if cooling else 0, nu, Tu, tu)
 
 
 def _check_state(U):
@@ -165,6 +171,20 @@ def clamp_h2(P, U):
 def chemistry(P, U, dt):
     lib().orc_chemistry(ctypes.byref(P), _p(U), float(dt))
     return U
+
+
+def cooling(P, U, dt):
+    """Heating/cooling stage (explicit Euler), in place."""
+    _check_state(U)
+    lib().orc_cooling(ctypes.byref(P), _p(U), float(dt))
+    return U
+
+
+def heat_cool(P, rho, e, h2):
+    """Gamma - Lambda (erg cm^-3 s^-1) and the terms (Gamma1, Gamma4, Lambda2, Lambda3, T)."""
+    out = np.zeros(5)
+    r = lib().orc_heat_cool(ctypes.byref(P), float(rho), float(e), float(h2), _p(out))
+    return r, out
 
 
 def regularise(P, U):

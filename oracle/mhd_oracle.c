@@ -67,6 +67,23 @@
  *            with mu = 1 / (1 - x_H2/2), time unit t_u seconds.
  *   R-cfl    Sec. 2.3: verbatim speed sum v + b + c + c_a + c_s + c_f with
  *            c_a from the x component of the cell-centre field.
+ *   R-cool   Sec. 2 stage 5, Sec. 2.8 and the appendix heating/cooling of
+ *            reactions 1-4: the stage runs after chemistry and before
+ *            regularisation; Gamma - Lambda is evaluated once per cell at the
+ *            state entering it and held over tau (explicit Euler); the code
+ *            energy density unit is n_u k_B T_u; cooling never takes e below
+ *            the internal energy at 10 K (or below e if already colder); E
+ *            gets the change e took.  x = log10(T / 1e4).  Gamma1 = 7.2e-12 erg
+ *            x (formation rate C of reaction 1) / (1 + n_cr / n) with
+ *            n_cr = 10^(4 - 0.416 x - 0.327 x^2) (the printed form drops the
+ *            rate and the power of ten).  Lambda2 verbatim.  Lambda3: k_H is
+ *            undefined in print and read as k_H = k_H2; f(T) = sqrt(T) a
+ *            exp(-a) with a = 1 + 1/(k_B T), k_B T in eV (the printed exp(+a)
+ *            grows without bound as T -> 0, unlike an excitation rate, and
+ *            gives cooling times of 1e7 s at 700 K).  Gamma4 = 6.4e-13 erg k4
+ *            n_H2.  The
+ *            terms of reactions 5-8 belong to the ionisation network, which
+ *            is not built.
  *
  * Layout: the state is 10 structure-of-arrays fields of nx*ny*nz doubles,
  * x fastest: rho, mx, my, mz, E, e (= rho eps), bx, by, bz, h2 (= rho_H2).
@@ -86,6 +103,7 @@ typedef struct {
     double cfl;
     double theta;
     int chemistry;
+    int cooling;     /* subgrid heating/cooling stage (Sec. 2.8) on/off */
     double n_unit;   /* H nuclei per cm^3 per unit code density */
     double T_unit;   /* K: T = T_unit * mu * p / rho            */
     double t_unit;   /* s per code time unit                    */
@@ -675,6 +693,102 @@ double orc_chem_cell(const orc_params *P, double rho, double e, double h2, doubl
     return 2.0 * nn / P->n_unit;
 }
 
+/* ------------------------------------------------------------------ */
+/* Sec. 2 stage 5 and Sec. 2.8 ("subgrid physics") with the appendix    */
+/* heating and cooling functions of reactions 1-4 (erg cm^-3 s^-1).      */
+/* ------------------------------------------------------------------ */
+#define ORC_KB_ERG 1.380649e-16      /* Boltzmann constant, erg / K  */
+#define ORC_KB_EV 8.617333262e-5     /* Boltzmann constant, eV / K   */
+#define ORC_T_FLOOR 10.0             /* K: lower bound of the cooling */
+
+/* critical density of the H2 formation heating, 10^(4 - 0.416 x - 0.327 x^2) cm^-3, x = log10(T / 1e4) */
+double orc_ncrit(double T)
+{
+    double x = log10(T / 1e4);
+    return pow(10.0, 4.0 - 0.416 * x - 0.327 * x * x);
+}
+
+/* reaction 2 cooling: high- and low-density limits L_H, L_L (erg s^-1 per H2) */
+double orc_lh2(double T)
+{
+    double x = log10(T / 1e4);
+    if (T > 1087.0) return 3.9e-19 * exp(-6118.0 / T);
+    return pow(10.0, -19.24 + 0.474 * x - 1.247 * x * x);
+}
+
+double orc_ll2(double T, double nH, double nH2)
+{
+    double x = log10(T / 1e4);
+    double f = (T > 4031.0) ? 1.38e-22 * exp(-9243.0 / T) : pow(10.0, -22.9 - 0.553 * x - 1.148 * x * x);
+    return (pow(nH2, 0.77) + 1.2 * pow(nH, 0.77)) * f;
+}
+
+/* reaction 3 cooling: log of the low-density limit L_L = 8.18e-13 (n_H k_H + n_H2 k_H2)
+ * with k_H = k_H2 = 6.29e-15 * 1.38 * f(T) / f(4500), f(T) = sqrt(T) a exp(-a),
+ * a = 1 + 1 / (k_B T) with k_B T in eV (exp(-a): a collisional excitation
+ * rate falls with temperature); kept in logarithms because f underflows at
+ * low temperature */
+static double orc_lnf3(double T)
+{
+    double a = 1.0 + 1.0 / (ORC_KB_EV * T);
+    return 0.5 * log(T) + log(a) - a;
+}
+
+double orc_ln_ll3(double T, double n)
+{
+    return log(8.18e-13) + log(n) + log(6.29e-15 * 1.38) + orc_lnf3(T) - orc_lnf3(4500.0);
+}
+
+/* Gamma - Lambda of one cell (erg cm^-3 s^-1) at its current state.
+ * terms_out (optional): Gamma1, Gamma4, Lambda2, Lambda3, T. */
+double orc_heat_cool(const orc_params *P, double rho, double e, double h2, double *terms_out)
+{
+    double p = (P->gamma - 1.0) * e;
+    double mu = 1.0 / (1.0 - 0.5 * (h2 / rho));
+    double T = P->T_unit * mu * p / rho;
+    double nH = P->n_unit * (rho - h2);
+    double nH2 = P->n_unit * h2 / 2.0;
+    double n = nH + nH2;
+    /* Gamma1: 7.2e-12 erg per H2 formed, times the formation rate C of
+     * reaction 1, times the fraction 1 / (1 + n_cr / n) */
+    double g1 = 7.2e-12 * (orc_k1_base(T) * n * nH) / (1.0 + orc_ncrit(T) / n);
+    /* Gamma4: 6.4e-13 erg per photodissociation */
+    double g4 = 6.4e-13 * orc_k4() * nH2;
+    /* Lambda2 = n_H2 L_H / (1 + L_H / L_L) */
+    double lh2 = orc_lh2(T);
+    double l2 = nH2 * lh2 / (1.0 + lh2 / orc_ll2(T, nH, nH2));
+    /* Lambda3 = n_H2 L_H / (1 + L_H / L_L), L_H = 1.1e-13 exp(-6744 / T) */
+    double ln_lh3 = log(1.1e-13) - 6744.0 / T;
+    double l3 = nH2 * exp(ln_lh3) / (1.0 + exp(ln_lh3 - orc_ln_ll3(T, n)));
+    if (terms_out) {
+        terms_out[0] = g1; terms_out[1] = g4; terms_out[2] = l2; terms_out[3] = l3; terms_out[4] = T;
+    }
+    return (g1 + g4) - (l2 + l3);
+}
+
+/* Sec. 2.8: explicit Euler step of d(rho eps)/dt = d(rho E)/dt = Gamma - Lambda
+ * with the rates frozen over dt.  The code energy density unit is
+ * n_u k_B T_u; cooling stops at the internal energy of T_floor (or at the
+ * current one if the cell is already colder), and E takes the change that e
+ * actually took. */
+void orc_cooling(const orc_params *P, double *U, double dt)
+{
+    const size_t N = ncell(P);
+    const double eu = P->n_unit * ORC_KB_ERG * P->T_unit;
+    #pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < N; c++) {
+        double rho = U[F_RHO * N + c], e = U[F_EI * N + c], h2 = U[F_H2 * N + c];
+        double de = dt * P->t_unit * orc_heat_cool(P, rho, e, h2, NULL) / eu;
+        double mu = 1.0 / (1.0 - 0.5 * (h2 / rho));
+        double efloor = rho * ORC_T_FLOOR / (P->T_unit * mu * (P->gamma - 1.0));
+        double lo = e < efloor ? e : efloor;
+        double en = e + de;
+        if (en < lo) en = lo;
+        U[F_E * N + c] += en - e;
+        U[F_EI * N + c] = en;
+    }
+}
+
 /* clamp of the advected H2 density to [0, rho] (total hydrogen closure) */
 void orc_clamp_h2(const orc_params *P, double *U)
 {
@@ -757,9 +871,9 @@ double orc_cfl_dt(const orc_params *P, const double *U)
 }
 
 /* ------------------------------------------------------------------ */
-/* Sec. 2 list of stages: one operator-split step (no gravity, no        */
-/* heating/cooling): NONADV (with the face-field update inside),        */
-/* ADV, H2 clamp, chemistry, regularisation.                            */
+/* Sec. 2 list of stages: one operator-split step (no gravity):         */
+/* NONADV (with the face-field update inside), ADV, H2 clamp,           */
+/* chemistry, heating/cooling (optional), regularisation.               */
 /* ------------------------------------------------------------------ */
 void orc_step(const orc_params *P, double *U, double dt)
 {
@@ -767,6 +881,7 @@ void orc_step(const orc_params *P, double *U, double dt)
     orc_adv_stage(P, U, dt);
     orc_clamp_h2(P, U);
     if (P->chemistry) orc_chemistry(P, U, dt);
+    if (P->cooling) orc_cooling(P, U, dt);
     orc_regularise(P, U);
 }
 
