@@ -66,7 +66,8 @@ enum { MHD_FP64 = 0, MHD_FP32_MIXED = 1 };
 enum {
     MHD_STAGE_NONADV = 1,    /* the NONADV Runge-Kutta stage only                   */
     MHD_STAGE_ADV = 2,       /* the ADV Runge-Kutta stage only                      */
-    MHD_STAGE_TAIL = 3,      /* H2 clamp, chemistry (if enabled), regularisation    */
+    MHD_STAGE_TAIL = 3,      /* H2 clamp, chemistry and heating/cooling (if         */
+                             /* enabled), regularisation                            */
     MHD_STAGE_NONADV_RHS = 4,/* one NONADV substage from the current state: writes  */
                              /* tau R(U) into the state slots (rho, h2 slots zero)  */
     MHD_STAGE_ADV_RHS = 5    /* one ADV substage: tau R(U) (face-field slots zero)  */
@@ -81,6 +82,11 @@ typedef struct {
     double theta;            /* time coupling of the parabola averages: width           */
                              /* theta*|lambda|*tau (1 = the paper, 0 = edge values)     */
     int32_t chemistry;       /* 0 or 1                                                   */
+    int32_t cooling;         /* 0 or 1: subgrid heating/cooling stage (Sec. 2 stage 5,  */
+                             /* Sec. 2.8) after chemistry: explicit Euler step of        */
+                             /* d(rho eps)/dt = d(rho E)/dt = Gamma - Lambda with the     */
+                             /* appendix heating/cooling of reactions 1-4, FP64, energy  */
+                             /* unit n_unit k_B T_unit, floor at 10 K                     */
     double n_unit_cm3;       /* H nuclei per cm^3 per unit code density                 */
     double T_unit_K;         /* T = T_unit_K * mu * p / rho, mu = 1/(1 - x_H2/2)         */
     double t_unit_s;         /* seconds per code time unit                               */
@@ -122,7 +128,7 @@ int mhd_get_state(mhd_box *b, double *cons_out);
 int mhd_cfl_dt(mhd_box *b, double *dt_out);
 
 /* Advance the state by dt: NONADV, ADV, H2 clamp to [0, rho], chemistry,
- * regularisation; then the CFL step of the new state is computed on the
+ * heating/cooling (if enabled), regularisation; then the CFL step of the new state is computed on the
  * device.  Asynchronous.  dt must be finite and > 0 (else MHD_EINVAL); a dt
  * above the CFL bound of the start state (relative slack 1e-12 for MHD_FP64,
  * 1e-4 for MHD_FP32_MIXED, whose bound comes from FP32 values) latches
@@ -149,7 +155,7 @@ enum {
     MHD_K_NONADV_UPDATE = 2, /* NONADV flux/CT update + RK            */
     MHD_K_ADV_FACE = 3,      /* ADV face fluxes (per axis)            */
     MHD_K_ADV_UPDATE = 4,    /* ADV update + RK                       */
-    MHD_K_TAIL = 5,          /* clamp, chemistry, regularisation, CFL */
+    MHD_K_TAIL = 5,          /* clamp, chemistry, heating/cooling, regularisation, CFL */
     MHD_K_REDUCE = 6,        /* CFL / totals reductions               */
     MHD_NKCLASS = 7
 };
@@ -185,6 +191,7 @@ typedef struct {
     int32_t precision;       /* MHD_FP64 or MHD_FP32_MIXED                       */
     double gamma, cfl, theta;
     int32_t chemistry;
+    int32_t cooling;         /* as in mhd_params                                  */
     double n_unit_cm3, T_unit_K, t_unit_s;
     int32_t max_slots;       /* boxes in flight at most, 1..1024                 */
     void *stream;            /* hipStream_t; NULL = the null stream             */

@@ -35,6 +35,7 @@ class MhdParams(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("theta", ctypes.c_double),
         ("chemistry", ctypes.c_int32),
+        ("cooling", ctypes.c_int32),
         ("n_unit_cm3", ctypes.c_double),
         ("T_unit_K", ctypes.c_double),
         ("t_unit_s", ctypes.c_double),
@@ -51,6 +52,7 @@ class ServerParams(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("theta", ctypes.c_double),
         ("chemistry", ctypes.c_int32),
+        ("cooling", ctypes.c_int32),
         ("n_unit_cm3", ctypes.c_double),
         ("T_unit_K", ctypes.c_double),
         ("t_unit_s", ctypes.c_double),
@@ -149,12 +151,14 @@ def _check(status, what):
         raise MhdError(status, what)
 
 
-def make_params(shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None):
+def make_params(shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None,
+                cooling=False):
     nz, ny, nx = shape
     p = MhdParams()
     p.n[0], p.n[1], p.n[2] = nx, ny, nz
     p.gamma, p.cfl, p.precision, p.theta = gamma, cfl, precision, theta
     p.chemistry = 1 if chemistry else 0
+    p.cooling = 1 if cooling else 0
     p.n_unit_cm3, p.T_unit_K, p.t_unit_s = units if units is not None else DEFAULT_UNITS
     return p
 
@@ -167,10 +171,10 @@ class Box:
     """One periodic box on one GPU.  shape = (nz, ny, nx)."""
 
     def __init__(self, shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True,
-                 units=None, device="cuda", stream=None, workspace=None):
+                 units=None, device="cuda", stream=None, workspace=None, cooling=False):
         import torch
         self.shape = tuple(int(s) for s in shape)
-        self.p = make_params(self.shape, precision, gamma, cfl, theta, chemistry, units)
+        self.p = make_params(self.shape, precision, gamma, cfl, theta, chemistry, units, cooling)
         nbytes = workspace_bytes(self.p)
         if nbytes == 0:
             raise MhdError(MHD_EINVAL, "mhd_workspace_bytes")
@@ -256,10 +260,11 @@ class Box:
 
 
 def server_params(precision=FP32_MIXED, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None,
-                  max_slots=64):
+                  max_slots=64, cooling=False):
     p = ServerParams()
     p.precision, p.gamma, p.cfl, p.theta = precision, gamma, cfl, theta
     p.chemistry = 1 if chemistry else 0
+    p.cooling = 1 if cooling else 0
     p.n_unit_cm3, p.T_unit_K, p.t_unit_s = units if units is not None else DEFAULT_UNITS
     p.max_slots = max_slots
     return p

@@ -77,15 +77,16 @@ struct Layout {
     size_t slot, W, F, part, misc, total;
 };
 
-bool valid_physics(int32_t precision, double gamma, double cfl, double theta, int32_t chem, double nu, double Tu,
-                   double tu)
+bool valid_physics(int32_t precision, double gamma, double cfl, double theta, int32_t chem, int32_t cool,
+                   double nu, double Tu, double tu)
 {
     if (!(gamma > 1.0) || !std::isfinite(gamma)) return false;
     if (!(cfl > 0.0) || !std::isfinite(cfl)) return false;
     if (!(theta >= 0.0) || !std::isfinite(theta)) return false;
     if (precision != MHD_FP64 && precision != MHD_FP32_MIXED) return false;
     if (chem != 0 && chem != 1) return false;
-    if (chem && !(nu > 0.0 && Tu > 0.0 && tu > 0.0)) return false;
+    if (cool != 0 && cool != 1) return false;
+    if ((chem || cool) && !(nu > 0.0 && Tu > 0.0 && tu > 0.0)) return false;
     return true;
 }
 
@@ -100,8 +101,8 @@ bool valid_dims(const int32_t n[3])
 bool valid_params(const mhd_params* p)
 {
     if (!p || !valid_dims(p->n)) return false;
-    return valid_physics(p->precision, p->gamma, p->cfl, p->theta, p->chemistry, p->n_unit_cm3, p->T_unit_K,
-                         p->t_unit_s);
+    return valid_physics(p->precision, p->gamma, p->cfl, p->theta, p->chemistry, p->cooling, p->n_unit_cm3,
+                         p->T_unit_K, p->t_unit_s);
 }
 
 Layout layout_of(const int32_t n[3], int precision)
@@ -199,6 +200,7 @@ ChemArgs chem_args(mhd_box* b)
 {
     ChemArgs c;
     c.on = b->p.chemistry;
+    c.cool = b->p.cooling;
     c.n_unit = b->p.n_unit_cm3;
     c.T_unit = b->p.T_unit_K;
     c.t_unit = b->p.t_unit_s;
@@ -730,6 +732,7 @@ mhd_params box_params(const mhd_server* sv, const int32_t n[3], void* ws, size_t
     bp.precision = sv->p.precision;
     bp.theta = sv->p.theta;
     bp.chemistry = sv->p.chemistry;
+    bp.cooling = sv->p.cooling;
     bp.n_unit_cm3 = sv->p.n_unit_cm3;
     bp.T_unit_K = sv->p.T_unit_K;
     bp.t_unit_s = sv->p.t_unit_s;
@@ -1001,8 +1004,8 @@ int mhd_server_create(const mhd_server_params* p, mhd_server** out)
     if (!out) return MHD_EINVAL;
     *out = nullptr;
     if (!p) return MHD_EINVAL;
-    if (!valid_physics(p->precision, p->gamma, p->cfl, p->theta, p->chemistry, p->n_unit_cm3, p->T_unit_K,
-                       p->t_unit_s))
+    if (!valid_physics(p->precision, p->gamma, p->cfl, p->theta, p->chemistry, p->cooling, p->n_unit_cm3,
+                       p->T_unit_K, p->t_unit_s))
         return MHD_EINVAL;
     if (p->max_slots < 1 || p->max_slots > SERVER_MAX_SLOTS) return MHD_EINVAL;
     if (!p->workspace || p->workspace_bytes < SERVER_TAB_BYTES + 4096) return MHD_ENOMEM;

@@ -721,6 +721,13 @@ struct BTail {
                 h2 = h2 > rho ? rho : h2;
                 h2 = h2 < 0.0 ? 0.0 : h2;
                 if (A.ch.on) h2 = chem_h2(A.ch, A.a.gamma, rho, e, h2, step_dt(A.a));
+                if (A.ch.cool) {
+                    double en = cooled_e(A.ch, A.a.gamma, rho, e, h2, step_dt(A.a));
+                    E += en - e;
+                    e = en;
+                    U.f[EN][c] = (T)E;
+                    E = (double)(T)E;
+                }
                 double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
                 double M = 0.5 * (bx * bx + by * by + bz * bz);
                 double ei = E - K - M;

@@ -361,7 +361,8 @@ __device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr,
 // ---------------------------------------------------------------- FP64 per-cell physics
 
 struct ChemArgs {
-    int on;
+    int on;     // chemistry stage
+    int cool;   // heating/cooling stage
     double n_unit, T_unit, t_unit;
 };
 
@@ -390,6 +391,60 @@ __device__ double chem_h2(const ChemArgs& ch, double gamma, double rho, double e
     nn = nn > nmax ? nmax : nn;
     nn = nn < 0.0 ? 0.0 : nn;
     return 2.0 * nn / ch.n_unit;
+}
+
+// Sec. 2 stage 5 and Sec. 2.8 with the appendix heating and cooling of
+// reactions 1-4 (erg cm^-3 s^-1, x = log10(T / 1e4)): H2 formation heating
+// 7.2e-12 erg per formed molecule (formation rate of reaction 1) thermalised
+// by the fraction 1 / (1 + n_cr / n), n_cr = 10^(4 - 0.416 x - 0.327 x^2);
+// photodissociation heating 6.4e-13 erg per event; the two cooling terms
+// n_H2 L_H / (1 + L_H / L_L) of reactions 2 and 3.  In reaction 3's low-density
+// limit k_H = k_H2 = 6.29e-15 * 1.38 f(T) / f(4500), f = sqrt(T) a exp(-a),
+// a = 1 + 1 / (k_B T) with k_B T in eV, evaluated in logarithms.  Returns
+// Gamma - Lambda.
+__device__ double heat_cool(const ChemArgs& ch, double gamma, double rho, double e, double h2)
+{
+    const double kb_ev = 8.617333262e-5;
+    double p = (gamma - 1.0) * e;
+    double mu = 1.0 / (1.0 - 0.5 * (h2 / rho));
+    double T = ch.T_unit * mu * p / rho;
+    double nH = ch.n_unit * (rho - h2);
+    double nH2 = ch.n_unit * h2 / 2.0;
+    double n = nH + nH2;
+    double x = log10(T / 1e4);
+    double t2 = T / 100.0;
+    double st2 = sqrt(t2);
+    double k1b = 3e-17 * st2 / (1.0 + 0.4 * st2 + 0.2 * t2 + 0.08 * t2 * t2);
+    double ncr = pow(10.0, 4.0 - 0.416 * x - 0.327 * x * x);
+    double g1 = 7.2e-12 * (k1b * n * nH) / (1.0 + ncr / n);
+    double g4 = 6.4e-13 * (3.3 * 1.7e-11) * nH2;
+    double lh2 = (T > 1087.0) ? 3.9e-19 * exp(-6118.0 / T) : pow(10.0, -19.24 + 0.474 * x - 1.247 * x * x);
+    double fl2 = (T > 4031.0) ? 1.38e-22 * exp(-9243.0 / T) : pow(10.0, -22.9 - 0.553 * x - 1.148 * x * x);
+    double ll2 = (pow(nH2, 0.77) + 1.2 * pow(nH, 0.77)) * fl2;
+    double l2 = nH2 * lh2 / (1.0 + lh2 / ll2);
+    double a = 1.0 + 1.0 / (kb_ev * T);
+    const double a45 = 1.0 + 1.0 / (kb_ev * 4500.0);
+    double lnf = 0.5 * log(T) + log(a) - a;
+    double lnf45 = 0.5 * log(4500.0) + log(a45) - a45;
+    double ln_ll3 = log(8.18e-13) + log(n) + log(6.29e-15 * 1.38) + lnf - lnf45;
+    double ln_lh3 = log(1.1e-13) - 6744.0 / T;
+    double l3 = nH2 * exp(ln_lh3) / (1.0 + exp(ln_lh3 - ln_ll3));
+    return (g1 + g4) - (l2 + l3);
+}
+
+// explicit Euler step of the internal energy over dt with Gamma - Lambda
+// frozen; energy unit n_unit k_B T_unit; cooling stops at the internal energy
+// of 10 K, or at e where the cell is already colder
+__device__ double cooled_e(const ChemArgs& ch, double gamma, double rho, double e, double h2, double dt)
+{
+    const double kb = 1.380649e-16, t_floor = 10.0;
+    double eu = ch.n_unit * kb * ch.T_unit;
+    double de = dt * ch.t_unit * heat_cool(ch, gamma, rho, e, h2) / eu;
+    double mu = 1.0 / (1.0 - 0.5 * (h2 / rho));
+    double efloor = rho * t_floor / (ch.T_unit * mu * (gamma - 1.0));
+    double lo = e < efloor ? e : efloor;
+    double en = e + de;
+    return en < lo ? lo : en;
 }
 
 // Sec. 2.3: the speed sum of the CFL rule for one cell (FP64)

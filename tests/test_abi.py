@@ -27,7 +27,7 @@ def test_workspace_bytes_scales_with_cells_and_precision():
 
 
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("cfl", 0.0), ("theta", -1.0), ("precision", 7),
-                                         ("chemistry", 2)])
+                                         ("chemistry", 2), ("cooling", 2)])
 def test_invalid_parameters_rejected(field, value):
     p = binding.make_params((4, 4, 4))
     setattr(p, field, value)
