@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("theta", ctypes.c_double),
-        ("chemistry", ctypes.c_int), ("cooling", ctypes.c_int),
+        ("chemistry", ctypes.c_int), ("cooling", ctypes.c_int), ("grav_G", ctypes.c_double),
         ("n_unit", ctypes.c_double), ("T_unit", ctypes.c_double), ("t_unit", ctypes.c_double),
     ]
 
@@ -79,6 +79,8 @@ def lib():
             ("orc_ln_ll3", [ctypes.c_double] * 2, ctypes.c_double),
             ("orc_heat_cool", [P] + [ctypes.c_double] * 3 + [_D], ctypes.c_double),
             ("orc_cooling", [P, _D, ctypes.c_double], None),
+            ("orc_potential", [P, _D, _D], None),
+            ("orc_stencil_factor", [ctypes.c_int, ctypes.c_int], ctypes.c_double),
             ("orc_clamp_h2", [P, _D], None),
             ("orc_chemistry", [P, _D, ctypes.c_double], None),
             ("orc_regularise", [P, _D], None),
@@ -108,10 +110,17 @@ def default_units():
     return 5.0, T_u, 256.0 * pc / v_u
 
 
-def make_params(shape, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None, cooling=False):
+def gravity_G(units=None):
+    """G in code units, G_cgs n_u m_H t_u^2 (density unit n_u m_H g cm^-3, time unit t_u s)."""
+    nu, Tu, tu = units if units is not None else default_units()
+    return 6.6743e-8 * nu * 1.6735575e-24 * tu * tu
+
+
+def make_params(shape, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None, cooling=False, grav_G=0.0):
     nz, ny, nx = shape
     nu, Tu, tu = units if units is not None else default_units()
-    return Params(nx, ny, nz, gamma, cfl, theta, 1 if chemistry else 0, 1 if cooling else 0, nu, Tu, tu)
+    return Params(nx, ny, nz, gamma, cfl, theta, 1 if chemistry else 0, 1 if cooling else 0, float(grav_G),
+                  nu, Tu, tu)
 
 
 def _check_state(U):
@@ -185,6 +194,14 @@ def heat_cool(P, rho, e, h2):
     out = np.zeros(5)
     r = lib().orc_heat_cool(ctypes.byref(P), float(rho), float(e), float(h2), _p(out))
     return r, out
+
+
+def potential(P, rho):
+    """Gravitational potential of the density field (Poisson stage)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    phi = np.empty_like(rho)
+    lib().orc_potential(ctypes.byref(P), _p(rho), _p(phi))
+    return phi
 
 
 def regularise(P, U):

@@ -84,6 +84,17 @@
  *            n_H2.  The
  *            terms of reactions 5-8 belong to the ionisation network, which
  *            is not built.
+ *   R-grav   Sec. 2 equations, Sec. 2.4 and Sec. 2.9: Laplace(Phi) = 4 pi G
+ *            rho; in harmonic space Phi_hat = -(2/3) pi G h^2 rho_hat /
+ *            (1 - prod_d (3 - 2 sin^2(pi m_d / n_d)) / 3) (the printed form
+ *            lacks the minus sign and G: it would put potential maxima on
+ *            density peaks), the zero mode set to zero (periodic box);
+ *            discrete Fourier transform of the periodic grid.  The potential
+ *            is that of the current density: the Poisson stage ends one step
+ *            and NONADV of the next reads it; rho does not change inside
+ *            NONADV.  Sources in every NONADV substage: -rho grad(Phi) on m,
+ *            -m . grad(Phi) on E, central differences (2h).  G in code
+ *            units is G_cgs n_u m_H t_u^2.
  *
  * Layout: the state is 10 structure-of-arrays fields of nx*ny*nz doubles,
  * x fastest: rho, mx, my, mz, E, e (= rho eps), bx, by, bz, h2 (= rho_H2).
@@ -95,6 +106,8 @@
 #include <string.h>
 #include <stddef.h>
 
+#define ORC_PI 3.14159265358979323846
+
 enum { F_RHO = 0, F_MX, F_MY, F_MZ, F_E, F_EI, F_BX, F_BY, F_BZ, F_H2, NF };
 
 typedef struct {
@@ -104,6 +117,7 @@ typedef struct {
     double theta;
     int chemistry;
     int cooling;     /* subgrid heating/cooling stage (Sec. 2.8) on/off */
+    double grav_G;   /* gravitational constant in code units; 0 = no self-gravity */
     double n_unit;   /* H nuclei per cm^3 per unit code density */
     double T_unit;   /* K: T = T_unit * mu * p / rho            */
     double t_unit;   /* s per code time unit                    */
@@ -374,6 +388,8 @@ static void unit_offset(int d, int o[3]) { o[0] = o[1] = o[2] = 0; o[d] = 1; }
 /* U: current substage state.  inc: tau * R(U) for mx,my,mz,E,e,bx,by,bz */
 /* stored in the field slots of a 10-field array (rho, h2 slots zero).   */
 /* ------------------------------------------------------------------ */
+void orc_potential(const orc_params *P, const double *rho, double *phi);
+
 static void nonadv_increment(const orc_params *P, const double *U, double dt, double *inc)
 {
     const size_t N = ncell(P);
@@ -524,6 +540,33 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
                 inc[F_RHO * N + c] = 0.0;
                 inc[F_H2 * N + c] = 0.0;
             }
+
+    /* Sec. 2 (momentum and energy equations) and Sec. 2.4: self-gravity
+     * sources -rho grad(Phi) and -rho v . grad(Phi) with central differences
+     * of the potential of the current density (rho is the same in every
+     * NONADV substage) */
+    if (P->grav_G > 0.0) {
+        double *phi = (double *)malloc(sizeof(double) * N);
+        orc_potential(P, U + F_RHO * N, phi);
+        #pragma omp parallel for collapse(2) schedule(static)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) {
+                    size_t c = cell(P, i, j, k);
+                    double g[3];
+                    g[0] = (phi[cell(P, i + 1, j, k)] - phi[cell(P, i - 1, j, k)]) / (2.0 * h);
+                    g[1] = (phi[cell(P, i, j + 1, k)] - phi[cell(P, i, j - 1, k)]) / (2.0 * h);
+                    g[2] = (phi[cell(P, i, j, k + 1)] - phi[cell(P, i, j, k - 1)]) / (2.0 * h);
+                    double rho = U[F_RHO * N + c];
+                    double work = 0.0;
+                    for (int a = 0; a < 3; a++) {
+                        inc[(size_t)(F_MX + a) * N + c] -= dt * rho * g[a];
+                        work += U[(size_t)(F_MX + a) * N + c] * g[a];
+                    }
+                    inc[F_E * N + c] -= dt * work;
+                }
+        free(phi);
+    }
 
     free(W);
     free(FS);
@@ -787,6 +830,85 @@ void orc_cooling(const orc_params *P, double *U, double dt)
         U[F_E * N + c] += en - e;
         U[F_EI * N + c] = en;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.9: Poisson equation Laplace(Phi) = 4 pi G rho with the 27-point */
+/* stencil, solved in harmonic space.  The discrete Fourier transform is  */
+/* written out as plain sums along each axis (no fast algorithm).         */
+/* ------------------------------------------------------------------ */
+
+/* in-place DFT of every grid line along axis d: X_m = sum_j x_j exp(sgn 2 pi i j m / n) */
+static void dft_axis(const orc_params *P, double *re, double *im, int d, int sgn)
+{
+    const int dims[3] = { P->nx, P->ny, P->nz };
+    const int n = dims[d];
+    const size_t stride = d == 0 ? 1 : (d == 1 ? (size_t)P->nx : (size_t)P->nx * P->ny);
+    const int o1 = dims[d == 0 ? 1 : 0], o2 = dims[d == 2 ? 1 : 2];
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int b = 0; b < o2; b++)
+        for (int a = 0; a < o1; a++) {
+            int idx[3];
+            idx[d] = 0;
+            idx[d == 0 ? 1 : 0] = a;
+            idx[d == 2 ? 1 : 2] = b;
+            size_t base = cell(P, idx[0], idx[1], idx[2]);
+            double *xr = (double *)malloc(sizeof(double) * 2 * n);
+            double *xi = xr + n;
+            for (int j = 0; j < n; j++) {
+                xr[j] = re[base + j * stride];
+                xi[j] = im[base + j * stride];
+            }
+            for (int m = 0; m < n; m++) {
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j < n; j++) {
+                    /* angle from the reduced integer product j m mod n */
+                    double t = 2.0 * ORC_PI * (double)(((long)j * m) % n) / (double)n;
+                    double c = cos(t), s = sgn * sin(t);
+                    sr += xr[j] * c - xi[j] * s;
+                    si += xr[j] * s + xi[j] * c;
+                }
+                re[base + m * stride] = sr;
+                im[base + m * stride] = si;
+            }
+            free(xr);
+        }
+}
+
+/* eigenvalue factor of the 27-point stencil along one axis: (3 - 2 sin^2(pi m / n)) / 3 */
+double orc_stencil_factor(int m, int n)
+{
+    double s = sin(ORC_PI * (double)m / (double)n);
+    return (3.0 - 2.0 * s * s) / 3.0;
+}
+
+/* Phi = sum over modes of -(2/3) pi G h^2 rho_hat / (1 - ax ay az), the zero
+ * mode (the mean density of the periodic box) set to zero */
+void orc_potential(const orc_params *P, const double *rho, double *phi)
+{
+    const size_t N = ncell(P);
+    const double h = 1.0 / (double)P->nx;
+    double *re = (double *)malloc(sizeof(double) * N);
+    double *im = (double *)calloc(N, sizeof(double));
+    memcpy(re, rho, sizeof(double) * N);
+    for (int d = 0; d < 3; d++) dft_axis(P, re, im, d, -1);
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                size_t c = cell(P, i, j, k);
+                double g = 0.0;
+                if (i != 0 || j != 0 || k != 0) {
+                    double a = orc_stencil_factor(i, P->nx) * orc_stencil_factor(j, P->ny) *
+                               orc_stencil_factor(k, P->nz);
+                    g = -(2.0 / 3.0) * ORC_PI * P->grav_G * h * h / (1.0 - a);
+                }
+                re[c] *= g;
+                im[c] *= g;
+            }
+    for (int d = 0; d < 3; d++) dft_axis(P, re, im, d, +1);
+    for (size_t c = 0; c < N; c++) phi[c] = re[c] / (double)N;
+    free(re);
+    free(im);
 }
 
 /* clamp of the advected H2 density to [0, rho] (total hydrogen closure) */
