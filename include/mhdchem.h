@@ -87,6 +87,13 @@ typedef struct {
                              /* d(rho eps)/dt = d(rho E)/dt = Gamma - Lambda with the     */
                              /* appendix heating/cooling of reactions 1-4, FP64, energy  */
                              /* unit n_unit k_B T_unit, floor at 10 K                     */
+    double grav_G;           /* self-gravity (Sec. 2 equations, Sec. 2.9): gravitational  */
+                             /* constant in code units, 0 = off.  When > 0 every step     */
+                             /* solves Laplace(Phi) = 4 pi G rho with the 27-point        */
+                             /* stencil in harmonic space (on-device FFT, zero-mean Phi)  */
+                             /* and NONADV adds -rho grad(Phi) to m and -m.grad(Phi) to E */
+                             /* (central differences).  Each n[d] must then be a power    */
+                             /* of two, at most 1024 (else MHD_EINVAL).                   */
     double n_unit_cm3;       /* H nuclei per cm^3 per unit code density                 */
     double T_unit_K;         /* T = T_unit_K * mu * p / rho, mu = 1/(1 - x_H2/2)         */
     double t_unit_s;         /* seconds per code time unit                               */
@@ -121,6 +128,12 @@ int mhd_set_state(mhd_box *b, const double *cons);
 /* Copy the current conserved state to host FP64 (10 fields).  Synchronises;
  * returns a latched fault if any. */
 int mhd_get_state(mhd_box *b, double *cons_out);
+
+/* Gravitational potential of the current density (Sec. 2.9: the Poisson
+ * stage run on the device), copied to phi_out: host FP64, nx*ny*nz values,
+ * x fastest, zero mean.  Synchronises.  MHD_EINVAL if the box has no
+ * self-gravity (grav_G == 0). */
+int mhd_get_potential(mhd_box *b, double *phi_out);
 
 /* CFL time step of the current state (Sec. 2.3): min over cells of
  * cfl*h / (|v| + b + c + c_a + c_s + c_f), b = |B|/sqrt(rho), c_a from B_x.
@@ -157,7 +170,8 @@ enum {
     MHD_K_ADV_UPDATE = 4,    /* ADV update + RK                       */
     MHD_K_TAIL = 5,          /* clamp, chemistry, heating/cooling, regularisation, CFL */
     MHD_K_REDUCE = 6,        /* CFL / totals reductions               */
-    MHD_NKCLASS = 7
+    MHD_K_POISSON = 7,       /* self-gravity: FFT Poisson solve       */
+    MHD_NKCLASS = 8
 };
 
 /* Enable (1) or disable (0) per-launch HIP-event timing of the step's

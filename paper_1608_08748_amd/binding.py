@@ -18,7 +18,7 @@ MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ECFL, MHD_ENONPHYS = 0, -1, -2,
 FP64, FP32_MIXED = 0, 1
 STAGE_NONADV, STAGE_ADV, STAGE_TAIL, STAGE_NONADV_RHS, STAGE_ADV_RHS = 1, 2, 3, 4, 5
 FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2")
-KCLASSES = ("prim", "nonadv_face", "nonadv_update", "adv_face", "adv_update", "tail", "reduce")
+KCLASSES = ("prim", "nonadv_face", "nonadv_update", "adv_face", "adv_update", "tail", "reduce", "poisson")
 NKCLASS = len(KCLASSES)
 
 # chemistry unit map: 5 H nuclei per cm^3 per unit density, T_u = 5000 K,
@@ -36,6 +36,7 @@ class MhdParams(ctypes.Structure):
         ("theta", ctypes.c_double),
         ("chemistry", ctypes.c_int32),
         ("cooling", ctypes.c_int32),
+        ("grav_G", ctypes.c_double),
         ("n_unit_cm3", ctypes.c_double),
         ("T_unit_K", ctypes.c_double),
         ("t_unit_s", ctypes.c_double),
@@ -114,6 +115,7 @@ def lib():
         "mhd_init_state": ([B, _D], ctypes.c_int),
         "mhd_set_state": ([B, _D], ctypes.c_int),
         "mhd_get_state": ([B, _D], ctypes.c_int),
+        "mhd_get_potential": ([B, _D], ctypes.c_int),
         "mhd_cfl_dt": ([B, _D], ctypes.c_int),
         "mhd_step": ([B, ctypes.c_double], ctypes.c_int),
         "mhd_step_cfl": ([B], ctypes.c_int),
@@ -151,14 +153,22 @@ def _check(status, what):
         raise MhdError(status, what)
 
 
+def gravity_G(units=None):
+    """Gravitational constant in code units, G_cgs n_u m_H t_u^2 (density unit
+    n_u m_H g cm^-3, time unit t_u s): about 0.845 for the default units."""
+    nu, Tu, tu = units if units is not None else DEFAULT_UNITS
+    return 6.6743e-8 * nu * _MH * tu * tu
+
+
 def make_params(shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None,
-                cooling=False):
+                cooling=False, grav_G=0.0):
     nz, ny, nx = shape
     p = MhdParams()
     p.n[0], p.n[1], p.n[2] = nx, ny, nz
     p.gamma, p.cfl, p.precision, p.theta = gamma, cfl, precision, theta
     p.chemistry = 1 if chemistry else 0
     p.cooling = 1 if cooling else 0
+    p.grav_G = float(grav_G)
     p.n_unit_cm3, p.T_unit_K, p.t_unit_s = units if units is not None else DEFAULT_UNITS
     return p
 
@@ -171,10 +181,10 @@ class Box:
     """One periodic box on one GPU.  shape = (nz, ny, nx)."""
 
     def __init__(self, shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True,
-                 units=None, device="cuda", stream=None, workspace=None, cooling=False):
+                 units=None, device="cuda", stream=None, workspace=None, cooling=False, grav_G=0.0):
         import torch
         self.shape = tuple(int(s) for s in shape)
-        self.p = make_params(self.shape, precision, gamma, cfl, theta, chemistry, units, cooling)
+        self.p = make_params(self.shape, precision, gamma, cfl, theta, chemistry, units, cooling, grav_G)
         nbytes = workspace_bytes(self.p)
         if nbytes == 0:
             raise MhdError(MHD_EINVAL, "mhd_workspace_bytes")
@@ -207,6 +217,12 @@ class Box:
         U = np.empty((10,) + self.shape, dtype=np.float64)
         _check(lib().mhd_get_state(self.h, U.ctypes.data_as(_D)), "mhd_get_state")
         return U
+
+    def potential(self):
+        """Gravitational potential of the current density (boxes with grav_G > 0)."""
+        phi = np.empty(self.shape, dtype=np.float64)
+        _check(lib().mhd_get_potential(self.h, phi.ctypes.data_as(_D)), "mhd_get_potential")
+        return phi
 
     def cfl_dt(self):
         dt = ctypes.c_double()

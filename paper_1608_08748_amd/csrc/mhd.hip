@@ -50,6 +50,10 @@ struct mhd_box {
     uint32_t* flags;
     double* dt_dev;
     double* tot_dev;
+    int grav;          // self-gravity on
+    char* phi;         // gravitational potential, N values
+    char* tw[3];       // per-axis FFT twiddles (n/2 complex values)
+    double* sf[3];     // per-axis 27-point stencil factors (n values)
     int cur[3];        // current slot of the groups H, M, B
     // per-launch event timing (mhd_set_timing)
     int timing;
@@ -74,8 +78,13 @@ int group_of(int f)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t slot, W, F, part, misc, total;
+    size_t slot, W, F, part, misc, grav, total;
 };
+
+bool pow2_upto(int n, int cap) { return n >= 1 && n <= cap && (n & (n - 1)) == 0; }
+
+// the FFT Poisson solve handles power-of-two axes up to 1024 cells
+constexpr int FFT_MAX = 1024;
 
 bool valid_physics(int32_t precision, double gamma, double cfl, double theta, int32_t chem, int32_t cool,
                    double nu, double Tu, double tu)
@@ -101,11 +110,15 @@ bool valid_dims(const int32_t n[3])
 bool valid_params(const mhd_params* p)
 {
     if (!p || !valid_dims(p->n)) return false;
+    if (!(p->grav_G >= 0.0) || !std::isfinite(p->grav_G)) return false;
+    if (p->grav_G > 0.0)
+        for (int d = 0; d < 3; d++)
+            if (!pow2_upto(p->n[d], FFT_MAX)) return false;
     return valid_physics(p->precision, p->gamma, p->cfl, p->theta, p->chemistry, p->cooling, p->n_unit_cm3,
                          p->T_unit_K, p->t_unit_s);
 }
 
-Layout layout_of(const int32_t n[3], int precision)
+Layout layout_of(const int32_t n[3], int precision, bool grav)
 {
     Layout L;
     size_t N = (size_t)n[0] * n[1] * n[2];
@@ -119,7 +132,14 @@ Layout layout_of(const int32_t n[3], int precision)
     L.F = 3 * fbytes > stage ? 3 * fbytes : stage;
     L.part = align256(nb * NF * sizeof(double));
     L.misc = 3 * 256;
-    L.total = 3 * L.slot + L.W + L.F + L.part + L.misc;
+    // self-gravity: the potential and the FFT tables (the complex scratch of
+    // the Poisson solve is the x face scratch, free at that point)
+    L.grav = 0;
+    if (grav) {
+        L.grav = align256(N * esz);
+        for (int d = 0; d < 3; d++) L.grav += align256((size_t)(n[d] / 2 + 1) * 2 * esz) + align256(n[d] * 8);
+    }
+    L.total = 3 * L.slot + L.W + L.F + L.part + L.misc + L.grav;
     return L;
 }
 
@@ -150,6 +170,23 @@ void box_bind(mhd_box* b, const mhd_params* p, const Layout& L)
     b->flags = reinterpret_cast<uint32_t*>(w);
     b->dt_dev = reinterpret_cast<double*>(w + 256);
     b->tot_dev = reinterpret_cast<double*>(w + 512);
+    w += L.misc;
+    b->grav = p->grav_G > 0.0;
+    b->phi = nullptr;
+    for (int d = 0; d < 3; d++) {
+        b->tw[d] = nullptr;
+        b->sf[d] = nullptr;
+    }
+    if (b->grav) {
+        b->phi = w;
+        w += align256((size_t)b->g.n * b->esz);
+        for (int d = 0; d < 3; d++) {
+            b->tw[d] = w;
+            w += align256((size_t)(p->n[d] / 2 + 1) * 2 * b->esz);
+            b->sf[d] = reinterpret_cast<double*>(w);
+            w += align256((size_t)p->n[d] * 8);
+        }
+    }
     b->cur[0] = b->cur[1] = b->cur[2] = 0;
     b->timing = 0;
     b->nev = 0;
@@ -410,6 +447,7 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
     ua.rk = rk;
     ua.dbg = dbg;
     ua.zt = ztile_of(b->g);
+    ua.phi = b->grav ? reinterpret_cast<const T*>(b->phi) : nullptr;
     e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
 }
 
@@ -500,9 +538,96 @@ void emit_tail(mhd_box* b, Emit& e, const StepArgs& a, int mode)
     e.template launch<BReduceDt>(MHD_K_REDUCE, 1, 0, ra);
 }
 
+int ilog2(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) l++;
+    return l;
+}
+
+// Poisson stage (Sec. 2.9) on the current density: x forward, y forward,
+// z forward + Green's function + z inverse, y inverse, x inverse
+template <typename T, class Emit>
+void emit_poisson(mhd_box* b, Emit& e)
+{
+    const Geo& g = b->g;
+    FftArgs<T> fa;
+    fa.g = g;
+    fa.rho = reinterpret_cast<const T*>(b->slot[b->cur[GH]]) + (size_t)RHO * g.n;
+    fa.Z = reinterpret_cast<Cx<T>*>(b->F[0]);
+    fa.phi = reinterpret_cast<T*>(b->phi);
+    for (int d = 0; d < 3; d++) {
+        fa.tw[d] = reinterpret_cast<const Cx<T>*>(b->tw[d]);
+        fa.sf[d] = b->sf[d];
+        fa.logn[d] = ilog2(b->p.n[d]);
+    }
+    const double h = 1.0 / (double)b->p.n[0];
+    fa.gscale = -(2.0 / 3.0) * M_PI * b->p.grav_G * h * h / (double)g.n;
+    fa.lpb = g.nx >= 1024 ? 1 : 1024 / g.nx;
+    const int lines = g.ny * g.nz;
+    const int xb = (lines + fa.lpb - 1) / fa.lpb;
+    const size_t xshm = 2 * (size_t)fa.lpb * g.nx * sizeof(Cx<T>);
+    e.template launch<BFftX<T, 0>>(MHD_K_POISSON, xb, xshm, fa);
+    // y and z passes: tx columns of a line set, 2 x tx x (n + 1) complex in LDS
+    auto tx_of = [&](int n) {
+        int t = 2048 / n;
+        t = t < 1 ? 1 : t;
+        return t > g.nx ? g.nx : t;
+    };
+    fa.tx = tx_of(g.ny);
+    e.template launch<BFftYZ<T, 1, 0>>(MHD_K_POISSON, ((g.nx + fa.tx - 1) / fa.tx) * g.nz,
+                                       2 * (size_t)fa.tx * (g.ny + 1) * sizeof(Cx<T>), fa);
+    fa.tx = tx_of(g.nz);
+    e.template launch<BFftYZ<T, 2, 2>>(MHD_K_POISSON, ((g.nx + fa.tx - 1) / fa.tx) * g.ny,
+                                       2 * (size_t)fa.tx * (g.nz + 1) * sizeof(Cx<T>), fa);
+    fa.tx = tx_of(g.ny);
+    e.template launch<BFftYZ<T, 1, 1>>(MHD_K_POISSON, ((g.nx + fa.tx - 1) / fa.tx) * g.nz,
+                                       2 * (size_t)fa.tx * (g.ny + 1) * sizeof(Cx<T>), fa);
+    e.template launch<BFftX<T, 1>>(MHD_K_POISSON, xb, xshm, fa);
+}
+
+// host-built FFT tables of a self-gravity box, uploaded on the box's stream;
+// the caller synchronises before `host` goes out of scope
+template <typename T>
+int upload_grav_tables(mhd_box* b, std::vector<double>& host)
+{
+    if (!b->grav) return MHD_OK;
+    for (int d = 0; d < 3; d++) {
+        const int n = b->p.n[d];
+        std::vector<T> tw((size_t)(n / 2 + 1) * 2, T(0));
+        for (int m = 0; m < n / 2; m++) {
+            const double t = 2.0 * M_PI * (double)m / (double)n;
+            tw[2 * m] = (T)std::cos(t);
+            tw[2 * m + 1] = (T)(-std::sin(t));
+        }
+        const size_t off = host.size();
+        host.resize(off + (tw.size() * sizeof(T) + 7) / 8 + n);
+        std::memcpy(host.data() + off, tw.data(), tw.size() * sizeof(T));
+        double* sfh = host.data() + off + (tw.size() * sizeof(T) + 7) / 8;
+        for (int m = 0; m < n; m++) {
+            const double s = std::sin(M_PI * (double)m / (double)n);
+            sfh[m] = (3.0 - 2.0 * s * s) / 3.0;
+        }
+    }
+    size_t off = 0;
+    for (int d = 0; d < 3; d++) {
+        const int n = b->p.n[d];
+        const size_t twb = (size_t)(n / 2 + 1) * 2 * sizeof(T);
+        if (hipMemcpyAsync(b->tw[d], host.data() + off, twb, hipMemcpyHostToDevice, b->s) != hipSuccess)
+            return MHD_EDEVICE;
+        off += (twb + 7) / 8;
+        if (hipMemcpyAsync(b->sf[d], host.data() + off, (size_t)n * 8, hipMemcpyHostToDevice, b->s) !=
+            hipSuccess)
+            return MHD_EDEVICE;
+        off += n;
+    }
+    return MHD_OK;
+}
+
 template <typename T, class Emit>
 void emit_step(mhd_box* b, Emit& e, const StepArgs& a)
 {
+    if (b->grav) emit_poisson<T>(b, e);
     emit_nonadv_stage<T>(b, e, a, true);
     emit_adv_stage<T>(b, e, a);
     emit_tail<T>(b, e, a, 1);
@@ -539,6 +664,9 @@ int load_f64(mhd_box* b, const double* host, bool prim)
     size_t nf = prim ? 9 : 10;
     if (hipMemcpyAsync(stage, host, nf * N * sizeof(double), hipMemcpyHostToDevice, b->s) != hipSuccess)
         return MHD_EDEVICE;
+    std::vector<double> tables;
+    int tst = upload_grav_tables<T>(b, tables);
+    if (tst) return tst;
     b->cur[GH] = b->cur[GM] = b->cur[GB] = 0;
     Fields<T> u = view<T>(b, 0, 0, 0);
     int saved = b->timing;
@@ -616,6 +744,7 @@ int debug_stage(mhd_box* b, int stage, double dt)
 {
     StepArgs a = step_args(b, dt, false);
     OneEmit e{ b };
+    if (b->grav && (stage == MHD_STAGE_NONADV || stage == MHD_STAGE_NONADV_RHS)) emit_poisson<T>(b, e);
     switch (stage) {
     case MHD_STAGE_NONADV: emit_nonadv_stage<T>(b, e, a, false); break;
     case MHD_STAGE_ADV: emit_adv_stage<T>(b, e, a); break;
@@ -733,6 +862,7 @@ mhd_params box_params(const mhd_server* sv, const int32_t n[3], void* ws, size_t
     bp.theta = sv->p.theta;
     bp.chemistry = sv->p.chemistry;
     bp.cooling = sv->p.cooling;
+    bp.grav_G = 0.0;   // served boxes run without self-gravity
     bp.n_unit_cm3 = sv->p.n_unit_cm3;
     bp.T_unit_K = sv->p.T_unit_K;
     bp.t_unit_s = sv->p.t_unit_s;
@@ -746,7 +876,7 @@ int server_admit(mhd_server* sv)
 {
     while (!sv->pending.empty() && (int)sv->active.size() < sv->p.max_slots) {
         mhd_server::Pending& q = sv->pending.front();
-        Layout L = layout_of(q.r.n, sv->p.precision);
+        Layout L = layout_of(q.r.n, sv->p.precision, false);
         size_t off;
         if (!pool_alloc(sv, L.total, &off)) break;   // first come, first served: wait for memory
         mhd_box* b = new (std::nothrow) mhd_box;
@@ -870,7 +1000,7 @@ extern "C" {
 size_t mhd_workspace_bytes(const mhd_params* p)
 {
     if (!valid_params(p)) return 0;
-    return layout_of(p->n, p->precision).total;
+    return layout_of(p->n, p->precision, p->grav_G > 0.0).total;
 }
 
 int mhd_create(const mhd_params* p, mhd_box** out)
@@ -878,7 +1008,7 @@ int mhd_create(const mhd_params* p, mhd_box** out)
     if (!out) return MHD_EINVAL;
     *out = nullptr;
     if (!valid_params(p)) return MHD_EINVAL;
-    Layout L = layout_of(p->n, p->precision);
+    Layout L = layout_of(p->n, p->precision, p->grav_G > 0.0);
     if (!p->workspace || p->workspace_bytes < L.total) return MHD_ENOMEM;
     if (((uintptr_t)p->workspace) & 255) return MHD_EINVAL;
     mhd_box* b = new (std::nothrow) mhd_box;
@@ -933,6 +1063,26 @@ int mhd_get_state(mhd_box* b, double* cons_out)
 {
     if (!b || !cons_out) return MHD_EINVAL;
     return b->prec == MHD_FP64 ? get_f64<double>(b, cons_out) : get_f64<float>(b, cons_out);
+}
+
+int mhd_get_potential(mhd_box* b, double* phi_out)
+{
+    if (!b || !phi_out || !b->grav) return MHD_EINVAL;
+    OneEmit e{ b };
+    const size_t N = (size_t)b->g.n;
+    if (b->prec == MHD_FP64) {
+        emit_poisson<double>(b, e);
+        if (launch_status()) return MHD_EDEVICE;
+        if (hipMemcpyAsync(phi_out, b->phi, N * 8, hipMemcpyDeviceToHost, b->s) != hipSuccess) return MHD_EDEVICE;
+        return sync_and_flags(b);
+    }
+    emit_poisson<float>(b, e);
+    if (launch_status()) return MHD_EDEVICE;
+    std::vector<float> tmp(N);
+    if (hipMemcpyAsync(tmp.data(), b->phi, N * 4, hipMemcpyDeviceToHost, b->s) != hipSuccess) return MHD_EDEVICE;
+    int st = sync_and_flags(b);
+    for (size_t c = 0; c < N; c++) phi_out[c] = (double)tmp[c];
+    return st;
 }
 
 int mhd_cfl_dt(mhd_box* b, double* dt_out)
@@ -996,7 +1146,7 @@ size_t mhd_server_box_bytes(const mhd_server_params* p, const int32_t n[3])
 {
     if (!p || !n || !valid_dims(n)) return 0;
     if (p->precision != MHD_FP64 && p->precision != MHD_FP32_MIXED) return 0;
-    return align256(layout_of(n, p->precision).total);
+    return align256(layout_of(n, p->precision, false).total);
 }
 
 int mhd_server_create(const mhd_server_params* p, mhd_server** out)
@@ -1035,7 +1185,7 @@ int mhd_server_submit(mhd_server* sv, const mhd_request* r, const double* prim, 
     if (!sv || !r || !prim || !id) return MHD_EINVAL;
     if (!valid_dims(r->n) || r->steps < 1) return MHD_EINVAL;
     if (r->n[0] > SERVER_MAX_NX) return MHD_EINVAL;
-    if (align256(layout_of(r->n, sv->p.precision).total) > sv->pool_bytes) return MHD_ENOMEM;
+    if (align256(layout_of(r->n, sv->p.precision, false).total) > sv->pool_bytes) return MHD_ENOMEM;
     mhd_server::Pending q;
     q.id = sv->next_id++;
     q.r = *r;

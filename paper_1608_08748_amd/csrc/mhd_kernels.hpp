@@ -409,6 +409,7 @@ struct BNonadvUpdate {
         RK rk;
         int dbg;
         ZTile zt;
+        const T* phi;   // gravitational potential, or null without self-gravity
     };
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -485,6 +486,22 @@ struct BNonadvUpdate {
             inc[BX] = -dtdx * (Ez_yp - Ez_c) + dtdx * (Ey_zp - Ey_c);
             inc[BY] = -dtdx * (Ex_zp - Ex_c) + dtdx * (Ez_xp - Ez_c);
             inc[BZ] = -dtdx * (Ey_xp - Ey_c) + dtdx * (Ex_yp - Ex_c);
+            if (A.phi) {
+                // self-gravity (Sec. 2 equations, Sec. 2.4): -rho grad(Phi) on
+                // m and -m . grad(Phi) on E, central differences
+                const T* ph = A.phi;
+                const T i2h = T(0.5 / A.a.h);
+                const T dt = T(step_dt(A.a));
+                T gv[3] = { (ph[xp] - ph[xm]) * i2h, (ph[yp] - ph[ym]) * i2h, (ph[zp] - ph[c + dzm]) * i2h };
+                T rho = A.U.f[RHO][c];
+                T work = T(0);
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    inc[MX + a] -= dt * rho * gv[a];
+                    work += A.U.f[MX + a][c] * gv[a];
+                }
+                inc[EN] -= dt * work;
+            }
 
             if (A.dbg) {
 #pragma unroll
@@ -503,6 +520,157 @@ struct BNonadvUpdate {
             for (int v = 0; v < 5; v++) fzc[v] = fzp[v];
             Ex_c = Ex_zp;
             Ey_c = Ey_zp;
+        }
+    }
+};
+
+// ---------------------------------------------------------------- Poisson (Sec. 2.9)
+
+template <typename T> struct Cx { T re, im; };
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(const Cx<T>& a, const Cx<T>& b)
+{
+    return { a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re };
+}
+
+// Radix-2 Stockham transform of nl lines of length n = 2^logn held in LDS
+// buffer a (line l at l * ls), ping-ponging with b; returns the buffer that
+// holds the result, in natural order.  tw[m] = exp(-2 pi i m / n), m < n/2;
+// inv conjugates the twiddles (no 1/n scaling).
+template <typename T>
+__device__ Cx<T>* stockham(Cx<T>* a, Cx<T>* b, int logn, int nl, int ls, const Cx<T>* __restrict__ tw, bool inv,
+                           int tid, int nt)
+{
+    const int half = (1 << logn) >> 1;
+    for (int st = 0; st < logn; st++) {
+        const int Ns = 1 << st;
+        for (int t = tid; t < nl * half; t += nt) {
+            const int l = t >> (logn - 1);
+            const int j = t & (half - 1);
+            const Cx<T>* in = a + l * ls;
+            Cx<T>* out = b + l * ls;
+            const int k = j & (Ns - 1);
+            Cx<T> w = tw[k << (logn - 1 - st)];
+            if (inv) w.im = -w.im;
+            const Cx<T> v0 = in[j];
+            const Cx<T> v1 = cmul(in[j + half], w);
+            const int o = ((j - k) << 1) + k;
+            out[o] = { v0.re + v1.re, v0.im + v1.im };
+            out[o + Ns] = { v0.re - v1.re, v0.im - v1.im };
+        }
+        __syncthreads();
+        Cx<T>* sw = a;
+        a = b;
+        b = sw;
+    }
+    return a;
+}
+
+template <typename T>
+struct FftArgs {
+    Geo g;
+    const T* rho;             // density (forward x pass)
+    Cx<T>* Z;                 // complex scratch, N values, cell order
+    T* phi;                   // potential (inverse x pass)
+    const Cx<T>* tw[3];       // per-axis twiddles
+    const double* sf[3];      // per-axis 27-point stencil factors (3 - 2 sin^2(pi m / n)) / 3
+    double gscale;            // -(2/3) pi G h^2 / N (Green's numerator with the 1/N of the inverse)
+    int logn[3];
+    int lpb;                  // x lines per block
+    int tx;                   // x columns per block of the y/z passes
+};
+
+// Transforms along x: INV = 0 reads the density and writes its transform to
+// Z; INV = 1 inverts Z and writes the real part, the potential.  Dynamic LDS:
+// 2 x lpb x nx complex values.
+template <typename T, int INV>
+struct BFftX {
+    static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
+    using Args = FftArgs<T>;
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
+    {
+        extern __shared__ unsigned char smem_raw[];
+        const int n = A.g.nx, logn = A.logn[0];
+        Cx<T>* a = reinterpret_cast<Cx<T>*>(smem_raw);
+        Cx<T>* b = a + A.lpb * n;
+        const int lines = A.g.ny * A.g.nz;
+        const int l0 = blk * A.lpb;
+        for (int t = tid; t < A.lpb * n; t += NT) {
+            const int line = l0 + (t >> logn);
+            Cx<T> v = { T(0), T(0) };
+            if (line < lines) {
+                const size_t c = (size_t)line * n + (t & (n - 1));
+                if (INV) v = A.Z[c];
+                else v.re = A.rho[c];
+            }
+            a[t] = v;
+        }
+        __syncthreads();
+        const Cx<T>* r = stockham(a, b, logn, A.lpb, n, A.tw[0], INV != 0, tid, NT);
+        for (int t = tid; t < A.lpb * n; t += NT) {
+            const int line = l0 + (t >> logn);
+            if (line >= lines) continue;
+            const size_t c = (size_t)line * n + (t & (n - 1));
+            if (INV) A.phi[c] = r[t].re;
+            else A.Z[c] = r[t];
+        }
+    }
+};
+
+// Transforms along D = y or z of tx adjacent x columns per block (row
+// segments of tx values are read and written together).  MODE 0: forward;
+// 1: inverse; 2 (D = z): forward, multiply by the Green's function of the
+// 27-point stencil, inverse.  Dynamic LDS: 2 x tx x (n + 1) complex values
+// (a padded line stride).
+template <typename T, int D, int MODE>
+struct BFftYZ {
+    static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
+    using Args = FftArgs<T>;
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
+    {
+        extern __shared__ unsigned char smem_raw[];
+        const Geo& g = A.g;
+        const int n = D == 1 ? g.ny : g.nz, logn = A.logn[D];
+        const int tx = A.tx, ls = n + 1;
+        Cx<T>* a = reinterpret_cast<Cx<T>*>(smem_raw);
+        Cx<T>* b = a + tx * ls;
+        const int ntx = (g.nx + tx - 1) / tx;
+        const int x0 = (blk % ntx) * tx;
+        const int o = blk / ntx;   // z index (D = y) or y index (D = z)
+        const size_t stride = D == 1 ? (size_t)g.nx : (size_t)g.nxy;
+        const size_t base = (size_t)x0 + (D == 1 ? (size_t)o * g.nxy : (size_t)o * g.nx);
+        for (int t = tid; t < tx * n; t += NT) {
+            const int p = t / tx, c = t - p * tx;
+            Cx<T> v = { T(0), T(0) };
+            if (x0 + c < g.nx) v = A.Z[base + p * stride + c];
+            a[c * ls + p] = v;
+        }
+        __syncthreads();
+        Cx<T>* r = stockham(a, b, logn, tx, ls, A.tw[D], MODE == 1, tid, NT);
+        if (MODE == 2) {
+            // mode (kx, ky, kz) = (x0 + c, o, p); the zero mode (the mean
+            // density of the periodic box) has no potential
+            for (int t = tid; t < tx * n; t += NT) {
+                const int c = t / n, p = t - c * n;
+                const int kx = x0 + c;
+                if (kx >= g.nx) continue;
+                double f = 0.0;
+                if (kx != 0 || o != 0 || p != 0)
+                    f = A.gscale / (1.0 - A.sf[0][kx] * A.sf[1][o] * A.sf[2][p]);
+                Cx<T>& v = r[c * ls + p];
+                v.re *= T(f);
+                v.im *= T(f);
+            }
+            __syncthreads();
+            Cx<T>* other = r == a ? b : a;
+            r = stockham(r, other, logn, tx, ls, A.tw[D], true, tid, NT);
+        }
+        for (int t = tid; t < tx * n; t += NT) {
+            const int p = t / tx, c = t - p * tx;
+            if (x0 + c < g.nx) A.Z[base + p * stride + c] = r[c * ls + p];
         }
     }
 };

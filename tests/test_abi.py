@@ -64,3 +64,20 @@ def test_strerror():
     for s in (0, -1, -2, -3, -4, -5):
         assert binding.strerror(s)
     assert binding.strerror(-99) == "unknown status"
+
+
+def test_gravity_parameters_validated():
+    ok = binding.make_params((8, 16, 32), grav_G=0.8)
+    base = binding.make_params((8, 16, 32))
+    assert binding.workspace_bytes(ok) > binding.workspace_bytes(base) > 0
+    for shape, G in (((8, 16, 24), 0.8), ((8, 16, 2048), 0.8), ((8, 8, 8), -1.0), ((8, 8, 8), float("nan")),
+                     ((8, 8, 8), float("inf"))):
+        p = binding.make_params(shape, grav_G=G)
+        assert binding.workspace_bytes(p) == 0, (shape, G)
+    # without gravity any shape is fine
+    assert binding.workspace_bytes(binding.make_params((8, 16, 24))) > 0
+
+
+def test_gravity_constant_in_code_units():
+    # G n_u m_H t_u^2 with n_u = 5 cm^-3, t_u = 256 pc / sqrt(k_B 5000 K / m_H)
+    assert abs(binding.gravity_G() - 0.84486) < 1e-4
