@@ -52,7 +52,7 @@ struct mhd_box {
     double* tot_dev;
     int grav;          // self-gravity on
     char* phi;         // gravitational potential, N values
-    char* tw[3];       // per-axis FFT twiddles (n/2 complex values)
+    char* tw[3];       // per-axis FFT twiddles (n complex values)
     double* sf[3];     // per-axis 27-point stencil factors (n values)
     int cur[3];        // current slot of the groups H, M, B
     // per-launch event timing (mhd_set_timing)
@@ -137,7 +137,7 @@ Layout layout_of(const int32_t n[3], int precision, bool grav)
     L.grav = 0;
     if (grav) {
         L.grav = align256(N * esz);
-        for (int d = 0; d < 3; d++) L.grav += align256((size_t)(n[d] / 2 + 1) * 2 * esz) + align256(n[d] * 8);
+        for (int d = 0; d < 3; d++) L.grav += align256((size_t)n[d] * 2 * esz) + align256(n[d] * 8);
     }
     L.total = 3 * L.slot + L.W + L.F + L.part + L.misc + L.grav;
     return L;
@@ -182,7 +182,7 @@ void box_bind(mhd_box* b, const mhd_params* p, const Layout& L)
         w += align256((size_t)b->g.n * b->esz);
         for (int d = 0; d < 3; d++) {
             b->tw[d] = w;
-            w += align256((size_t)(p->n[d] / 2 + 1) * 2 * b->esz);
+            w += align256((size_t)p->n[d] * 2 * b->esz);
             b->sf[d] = reinterpret_cast<double*>(w);
             w += align256((size_t)p->n[d] * 8);
         }
@@ -563,26 +563,26 @@ void emit_poisson(mhd_box* b, Emit& e)
     }
     const double h = 1.0 / (double)b->p.n[0];
     fa.gscale = -(2.0 / 3.0) * M_PI * b->p.grav_G * h * h / (double)g.n;
-    fa.lpb = g.nx >= 1024 ? 1 : 1024 / g.nx;
+    fa.lpb = g.nx >= FFT_X_VALUES ? 1 : FFT_X_VALUES / g.nx;
     const int lines = g.ny * g.nz;
     const int xb = (lines + fa.lpb - 1) / fa.lpb;
-    const size_t xshm = 2 * (size_t)fa.lpb * g.nx * sizeof(Cx<T>);
+    const size_t xshm = (size_t)fa.lpb * g.nx * sizeof(Cx<T>);
     e.template launch<BFftX<T, 0>>(MHD_K_POISSON, xb, xshm, fa);
-    // y and z passes: tx columns of a line set, 2 x tx x (n + 1) complex in LDS
+    // y and z passes: tx columns of a line set, tx x (n + 1) complex in LDS
     auto tx_of = [&](int n) {
-        int t = 2048 / n;
+        int t = FFT_YZ_VALUES / n;
         t = t < 1 ? 1 : t;
         return t > g.nx ? g.nx : t;
     };
     fa.tx = tx_of(g.ny);
     e.template launch<BFftYZ<T, 1, 0>>(MHD_K_POISSON, ((g.nx + fa.tx - 1) / fa.tx) * g.nz,
-                                       2 * (size_t)fa.tx * (g.ny + 1) * sizeof(Cx<T>), fa);
+                                       (size_t)fa.tx * (g.ny + 1) * sizeof(Cx<T>), fa);
     fa.tx = tx_of(g.nz);
     e.template launch<BFftYZ<T, 2, 2>>(MHD_K_POISSON, ((g.nx + fa.tx - 1) / fa.tx) * g.ny,
-                                       2 * (size_t)fa.tx * (g.nz + 1) * sizeof(Cx<T>), fa);
+                                       (size_t)fa.tx * (g.nz + 1) * sizeof(Cx<T>), fa);
     fa.tx = tx_of(g.ny);
     e.template launch<BFftYZ<T, 1, 1>>(MHD_K_POISSON, ((g.nx + fa.tx - 1) / fa.tx) * g.nz,
-                                       2 * (size_t)fa.tx * (g.ny + 1) * sizeof(Cx<T>), fa);
+                                       (size_t)fa.tx * (g.ny + 1) * sizeof(Cx<T>), fa);
     e.template launch<BFftX<T, 1>>(MHD_K_POISSON, xb, xshm, fa);
 }
 
@@ -594,8 +594,8 @@ int upload_grav_tables(mhd_box* b, std::vector<double>& host)
     if (!b->grav) return MHD_OK;
     for (int d = 0; d < 3; d++) {
         const int n = b->p.n[d];
-        std::vector<T> tw((size_t)(n / 2 + 1) * 2, T(0));
-        for (int m = 0; m < n / 2; m++) {
+        std::vector<T> tw((size_t)n * 2, T(0));
+        for (int m = 0; m < n; m++) {
             const double t = 2.0 * M_PI * (double)m / (double)n;
             tw[2 * m] = (T)std::cos(t);
             tw[2 * m + 1] = (T)(-std::sin(t));
@@ -612,7 +612,7 @@ int upload_grav_tables(mhd_box* b, std::vector<double>& host)
     size_t off = 0;
     for (int d = 0; d < 3; d++) {
         const int n = b->p.n[d];
-        const size_t twb = (size_t)(n / 2 + 1) * 2 * sizeof(T);
+        const size_t twb = (size_t)n * 2 * sizeof(T);
         if (hipMemcpyAsync(b->tw[d], host.data() + off, twb, hipMemcpyHostToDevice, b->s) != hipSuccess)
             return MHD_EDEVICE;
         off += (twb + 7) / 8;

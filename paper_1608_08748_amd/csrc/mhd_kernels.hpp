@@ -534,37 +534,95 @@ __device__ __forceinline__ Cx<T> cmul(const Cx<T>& a, const Cx<T>& b)
     return { a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re };
 }
 
-// Radix-2 Stockham transform of nl lines of length n = 2^logn held in LDS
-// buffer a (line l at l * ls), ping-ponging with b; returns the buffer that
-// holds the result, in natural order.  tw[m] = exp(-2 pi i m / n), m < n/2;
-// inv conjugates the twiddles (no 1/n scaling).
-template <typename T>
-__device__ Cx<T>* stockham(Cx<T>* a, Cx<T>* b, int logn, int nl, int ls, const Cx<T>* __restrict__ tw, bool inv,
-                           int tid, int nt)
+// Values (lines x length) one block transforms: 1024 in the x passes, 2048 in
+// the y/z passes, i.e. at most VALUES / 1024 radix-4 butterflies per thread of
+// a 256-thread block in a stage (twice that in the radix-2 stage)
+constexpr int FFT_X_VALUES = 1024;
+constexpr int FFT_YZ_VALUES = 2048;
+
+// Stockham transform of nl lines of length n = 2^logn held in the LDS buffer
+// a (line l at l * ls), in place: every thread first reads the inputs of all
+// its butterflies of a stage into registers, the block waits, then every
+// thread writes its outputs, and the block waits again.  Radix-4 stages, with
+// one radix-2 stage first when logn is odd; the result is in natural order.
+// tw[m] = exp(-2 pi i m / n), m < n; inv conjugates the twiddles (no 1/n
+// scaling).  Needs nl * n <= VALUES and nt = NTH.
+template <typename T, int VALUES>
+__device__ void stockham(Cx<T>* a, int logn, int nl, int ls, const Cx<T>* __restrict__ tw, bool inv, int tid,
+                         int nt)
 {
-    const int half = (1 << logn) >> 1;
-    for (int st = 0; st < logn; st++) {
-        const int Ns = 1 << st;
-        for (int t = tid; t < nl * half; t += nt) {
-            const int l = t >> (logn - 1);
-            const int j = t & (half - 1);
-            const Cx<T>* in = a + l * ls;
-            Cx<T>* out = b + l * ls;
-            const int k = j & (Ns - 1);
-            Cx<T> w = tw[k << (logn - 1 - st)];
-            if (inv) w.im = -w.im;
-            const Cx<T> v0 = in[j];
-            const Cx<T> v1 = cmul(in[j + half], w);
-            const int o = ((j - k) << 1) + k;
-            out[o] = { v0.re + v1.re, v0.im + v1.im };
-            out[o + Ns] = { v0.re - v1.re, v0.im - v1.im };
+    const int n = 1 << logn;
+    int Ns = 1;
+    if (logn & 1) {
+        // radix-2 stage with Ns = 1 (no twiddles)
+        constexpr int MB = VALUES / 2 / NTH;
+        const int half = n >> 1;
+        Cx<T> v[MB][2];
+#pragma unroll
+        for (int c = 0; c < MB; c++) {
+            const int t = tid + c * nt;
+            if (t < nl * half) {
+                const int l = t >> (logn - 1), j = t & (half - 1);
+                v[c][0] = a[l * ls + j];
+                v[c][1] = a[l * ls + j + half];
+            }
         }
         __syncthreads();
-        Cx<T>* sw = a;
-        a = b;
-        b = sw;
+#pragma unroll
+        for (int c = 0; c < MB; c++) {
+            const int t = tid + c * nt;
+            if (t < nl * half) {
+                const int l = t >> (logn - 1), j = t & (half - 1);
+                a[l * ls + 2 * j] = { v[c][0].re + v[c][1].re, v[c][0].im + v[c][1].im };
+                a[l * ls + 2 * j + 1] = { v[c][0].re - v[c][1].re, v[c][0].im - v[c][1].im };
+            }
+        }
+        __syncthreads();
+        Ns = 2;
     }
-    return a;
+    constexpr int MB = VALUES / 4 / NTH;
+    const int q = n >> 2;   // butterflies per line in a radix-4 stage
+    const int lq = logn - 2;
+    const T sgn = inv ? T(1) : T(-1);   // exp(sgn i pi / 2) = sgn i
+    for (; Ns < n; Ns <<= 2) {
+        const int tstep = n / (4 * Ns);   // twiddle index step of k
+        Cx<T> v[MB][4];
+#pragma unroll
+        for (int c = 0; c < MB; c++) {
+            const int t = tid + c * nt;
+            if (t < nl * q) {
+                const int l = t >> lq, j = t & (q - 1), k = j & (Ns - 1);
+#pragma unroll
+                for (int r = 0; r < 4; r++) v[c][r] = a[l * ls + j + r * q];
+#pragma unroll
+                for (int r = 1; r < 4; r++) {
+                    Cx<T> w = tw[r * k * tstep];
+                    if (inv) w.im = -w.im;
+                    v[c][r] = cmul(v[c][r], w);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < MB; c++) {
+            const int t = tid + c * nt;
+            if (t < nl * q) {
+                const int l = t >> lq, j = t & (q - 1), k = j & (Ns - 1);
+                // radix-4 DFT: X_r = sum_s v_s (sgn i)^(r s)
+                const Cx<T> s02 = { v[c][0].re + v[c][2].re, v[c][0].im + v[c][2].im };
+                const Cx<T> d02 = { v[c][0].re - v[c][2].re, v[c][0].im - v[c][2].im };
+                const Cx<T> s13 = { v[c][1].re + v[c][3].re, v[c][1].im + v[c][3].im };
+                const Cx<T> d13 = { v[c][1].re - v[c][3].re, v[c][1].im - v[c][3].im };
+                const Cx<T> rd = { -sgn * d13.im, sgn * d13.re };   // (sgn i) d13
+                const int o = l * ls + ((j - k) << 2) + k;
+                a[o] = { s02.re + s13.re, s02.im + s13.im };
+                a[o + Ns] = { d02.re + rd.re, d02.im + rd.im };
+                a[o + 2 * Ns] = { s02.re - s13.re, s02.im - s13.im };
+                a[o + 3 * Ns] = { d02.re - rd.re, d02.im - rd.im };
+            }
+        }
+        __syncthreads();
+    }
 }
 
 template <typename T>
@@ -573,7 +631,7 @@ struct FftArgs {
     const T* rho;             // density (forward x pass)
     Cx<T>* Z;                 // complex scratch, N values, cell order
     T* phi;                   // potential (inverse x pass)
-    const Cx<T>* tw[3];       // per-axis twiddles
+    const Cx<T>* tw[3];       // per-axis twiddles exp(-2 pi i m / n), m < n
     const double* sf[3];      // per-axis 27-point stencil factors (3 - 2 sin^2(pi m / n)) / 3
     double gscale;            // -(2/3) pi G h^2 / N (Green's numerator with the 1/N of the inverse)
     int logn[3];
@@ -583,7 +641,7 @@ struct FftArgs {
 
 // Transforms along x: INV = 0 reads the density and writes its transform to
 // Z; INV = 1 inverts Z and writes the real part, the potential.  Dynamic LDS:
-// 2 x lpb x nx complex values.
+// lpb x nx complex values.
 template <typename T, int INV>
 struct BFftX {
     static constexpr int NT = NTH;
@@ -594,21 +652,26 @@ struct BFftX {
         extern __shared__ unsigned char smem_raw[];
         const int n = A.g.nx, logn = A.logn[0];
         Cx<T>* a = reinterpret_cast<Cx<T>*>(smem_raw);
-        Cx<T>* b = a + A.lpb * n;
         const int lines = A.g.ny * A.g.nz;
         const int l0 = blk * A.lpb;
         for (int t = tid; t < A.lpb * n; t += NT) {
             const int line = l0 + (t >> logn);
-            Cx<T> v = { T(0), T(0) };
+            T re = T(0), im = T(0);
             if (line < lines) {
                 const size_t c = (size_t)line * n + (t & (n - 1));
-                if (INV) v = A.Z[c];
-                else v.re = A.rho[c];
+                if (INV) {
+                    re = A.Z[c].re;
+                    im = A.Z[c].im;
+                } else {
+                    re = A.rho[c];
+                }
             }
-            a[t] = v;
+            a[t].re = re;
+            a[t].im = im;
         }
         __syncthreads();
-        const Cx<T>* r = stockham(a, b, logn, A.lpb, n, A.tw[0], INV != 0, tid, NT);
+        stockham<T, FFT_X_VALUES>(a, logn, A.lpb, n, A.tw[0], INV != 0, tid, NT);
+        const Cx<T>* r = a;
         for (int t = tid; t < A.lpb * n; t += NT) {
             const int line = l0 + (t >> logn);
             if (line >= lines) continue;
@@ -622,8 +685,8 @@ struct BFftX {
 // Transforms along D = y or z of tx adjacent x columns per block (row
 // segments of tx values are read and written together).  MODE 0: forward;
 // 1: inverse; 2 (D = z): forward, multiply by the Green's function of the
-// 27-point stencil, inverse.  Dynamic LDS: 2 x tx x (n + 1) complex values
-// (a padded line stride).
+// 27-point stencil, inverse.  Dynamic LDS: tx x (n + 1) complex values (a
+// padded line stride).
 template <typename T, int D, int MODE>
 struct BFftYZ {
     static constexpr int NT = NTH;
@@ -636,7 +699,6 @@ struct BFftYZ {
         const int n = D == 1 ? g.ny : g.nz, logn = A.logn[D];
         const int tx = A.tx, ls = n + 1;
         Cx<T>* a = reinterpret_cast<Cx<T>*>(smem_raw);
-        Cx<T>* b = a + tx * ls;
         const int ntx = (g.nx + tx - 1) / tx;
         const int x0 = (blk % ntx) * tx;
         const int o = blk / ntx;   // z index (D = y) or y index (D = z)
@@ -644,12 +706,17 @@ struct BFftYZ {
         const size_t base = (size_t)x0 + (D == 1 ? (size_t)o * g.nxy : (size_t)o * g.nx);
         for (int t = tid; t < tx * n; t += NT) {
             const int p = t / tx, c = t - p * tx;
-            Cx<T> v = { T(0), T(0) };
-            if (x0 + c < g.nx) v = A.Z[base + p * stride + c];
-            a[c * ls + p] = v;
+            T re = T(0), im = T(0);
+            if (x0 + c < g.nx) {
+                re = A.Z[base + p * stride + c].re;
+                im = A.Z[base + p * stride + c].im;
+            }
+            a[c * ls + p].re = re;
+            a[c * ls + p].im = im;
         }
         __syncthreads();
-        Cx<T>* r = stockham(a, b, logn, tx, ls, A.tw[D], MODE == 1, tid, NT);
+        stockham<T, FFT_YZ_VALUES>(a, logn, tx, ls, A.tw[D], MODE == 1, tid, NT);
+        Cx<T>* r = a;
         if (MODE == 2) {
             // mode (kx, ky, kz) = (x0 + c, o, p); the zero mode (the mean
             // density of the periodic box) has no potential
@@ -665,8 +732,7 @@ struct BFftYZ {
                 v.im *= T(f);
             }
             __syncthreads();
-            Cx<T>* other = r == a ? b : a;
-            r = stockham(r, other, logn, tx, ls, A.tw[D], true, tid, NT);
+            stockham<T, FFT_YZ_VALUES>(a, logn, tx, ls, A.tw[D], true, tid, NT);
         }
         for (int t = tid; t < tx * n; t += NT) {
             const int p = t / tx, c = t - p * tx;
