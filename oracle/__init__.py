@@ -5,8 +5,8 @@ CPU-baseline leg of the benchmark load this module; the HIP library never
 does.  It shares nothing with the GPU path except the seeded input
 generators, which hold none of the method's arithmetic.
 
-State arrays are float64 of shape (10, nz, ny, nx) in field order
-rho, mx, my, mz, E, e, bx, by, bz, h2 (x fastest in memory).
+State arrays are float64 of shape (11, nz, ny, nx) in field order
+rho, mx, my, mz, E, e, bx, by, bz, h2, hp (x fastest in memory).
 """
 import ctypes
 import os
@@ -19,14 +19,15 @@ _SRC = os.path.join(_HERE, "mhd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2")
-NF = 10
+NF = 11
 
 
 class Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("theta", ctypes.c_double),
-        ("chemistry", ctypes.c_int), ("cooling", ctypes.c_int), ("grav_G", ctypes.c_double),
+        ("chemistry", ctypes.c_int), ("cooling", ctypes.c_int), ("ionisation", ctypes.c_int),
+        ("grav_G", ctypes.c_double),
         ("n_unit", ctypes.c_double), ("T_unit", ctypes.c_double), ("t_unit", ctypes.c_double),
     ]
 
@@ -80,6 +81,13 @@ def lib():
             ("orc_heat_cool", [P] + [ctypes.c_double] * 3 + [_D], ctypes.c_double),
             ("orc_cooling", [P, _D, ctypes.c_double], None),
             ("orc_potential", [P, _D, _D], None),
+            ("orc_gamma_cell", [P] + [ctypes.c_double] * 3, ctypes.c_double),
+            ("orc_k5", [], ctypes.c_double),
+            ("orc_k6", [ctypes.c_double], ctypes.c_double),
+            ("orc_k7", [ctypes.c_double], ctypes.c_double),
+            ("orc_k8", [ctypes.c_double], ctypes.c_double),
+            ("orc_chem_cell_ion", [P] + [ctypes.c_double] * 5 + [_D, _D, _D], None),
+            ("orc_heat_cool_ion", [P] + [ctypes.c_double] * 4 + [_D], ctypes.c_double),
             ("orc_stencil_factor", [ctypes.c_int, ctypes.c_int], ctypes.c_double),
             ("orc_clamp_h2", [P, _D], None),
             ("orc_chemistry", [P, _D, ctypes.c_double], None),
@@ -116,11 +124,12 @@ def gravity_G(units=None):
     return 6.6743e-8 * nu * 1.6735575e-24 * tu * tu
 
 
-def make_params(shape, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None, cooling=False, grav_G=0.0):
+def make_params(shape, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None, cooling=False, grav_G=0.0,
+                ionisation=False):
     nz, ny, nx = shape
     nu, Tu, tu = units if units is not None else default_units()
-    return Params(nx, ny, nz, gamma, cfl, theta, 1 if chemistry else 0, 1 if cooling else 0, float(grav_G),
-                  nu, Tu, tu)
+    return Params(nx, ny, nz, gamma, cfl, theta, 1 if chemistry else 0, 1 if cooling else 0,
+                  1 if ionisation else 0, float(grav_G), nu, Tu, tu)
 
 
 def _check_state(U):
@@ -202,6 +211,30 @@ def potential(P, rho):
     phi = np.empty_like(rho)
     lib().orc_potential(ctypes.byref(P), _p(rho), _p(phi))
     return phi
+
+
+def gamma_cell(P, rho, h2, hp):
+    return lib().orc_gamma_cell(ctypes.byref(P), float(rho), float(h2), float(hp))
+
+
+def ion_rates(T):
+    L = lib()
+    return L.orc_k5(), L.orc_k6(T), L.orc_k7(T), L.orc_k8(T)
+
+
+def chem_cell_ion(P, rho, e, h2, hp, dt):
+    """One cell of the chemistry with reactions 1-8: (h2', hp', rates)."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    rates = np.zeros(9)
+    lib().orc_chem_cell_ion(ctypes.byref(P), float(rho), float(e), float(h2), float(hp), float(dt),
+                            ctypes.byref(a), ctypes.byref(b), _p(rates))
+    return a.value, b.value, dict(zip(("k1b", "k2", "k3", "k4", "k5", "k6", "k7", "k8", "T"), rates))
+
+
+def heat_cool_ion(P, rho, e, h2, hp):
+    out = np.zeros(7)
+    r = lib().orc_heat_cool_ion(ctypes.byref(P), float(rho), float(e), float(h2), float(hp), _p(out))
+    return r, out
 
 
 def regularise(P, U):

@@ -95,9 +95,21 @@
  *            NONADV.  Sources in every NONADV substage: -rho grad(Phi) on m,
  *            -m . grad(Phi) on E, central differences (2h).  G in code
  *            units is G_cgs n_u m_H t_u^2.
+ *   R-ion    Sec. 4.3 + Appendix, reactions 5-8 (optional): H+ mass density
+ *            hp advected with the other ADV fields, n_e = n_H+ = n_u hp,
+ *            n_H = n_u (rho - h2 - hp), mean mass 1 / (1 - x_H2/2 + x_H+);
+ *            gamma_eff = (5 n_H + 5 n_e + 7 n_H2) / (3 n_H + 3 n_e + 5 n_H2) as
+ *            printed, per cell in p = (gamma - 1) e, the sound speed, the e
+ *            source, CFL and regularisation, the face value the sqrt(rho)-
+ *            weighted mean of the two cells'.  k5 = 6e-18 s^-1 per H atom; k6 the
+ *            printed polynomial in ln(T in eV); k7 and k8 as printed with log =
+ *            log10.  H+: C = k5 n_H + k6 n_H n_e, D = (k7 + k8) n_e, semi-
+ *            implicit with n_H, n_e frozen; H2 updated alongside with
+ *            n_H excluding the ions; n = n_H + n_H2 + n_H+.
  *
- * Layout: the state is 10 structure-of-arrays fields of nx*ny*nz doubles,
- * x fastest: rho, mx, my, mz, E, e (= rho eps), bx, by, bz, h2 (= rho_H2).
+ * Layout: the state is 11 structure-of-arrays fields of nx*ny*nz doubles,
+ * x fastest: rho, mx, my, mz, E, e (= rho eps), bx, by, bz, h2 (= rho_H2),
+ * hp (= rho_H+, zero and untouched without the ionisation network).
  * bx[i,j,k] is B_x on the face (i-1/2, j, k); by and bz likewise on the lower
  * y and z faces of the cell.
  */
@@ -108,7 +120,7 @@
 
 #define ORC_PI 3.14159265358979323846
 
-enum { F_RHO = 0, F_MX, F_MY, F_MZ, F_E, F_EI, F_BX, F_BY, F_BZ, F_H2, NF };
+enum { F_RHO = 0, F_MX, F_MY, F_MZ, F_E, F_EI, F_BX, F_BY, F_BZ, F_H2, F_HP, NF };
 
 typedef struct {
     int nx, ny, nz;
@@ -117,6 +129,7 @@ typedef struct {
     double theta;
     int chemistry;
     int cooling;     /* subgrid heating/cooling stage (Sec. 2.8) on/off */
+    int ionisation;  /* reactions 5-8 with H+ and e-, effective adiabatic index (Sec. 4.3) */
     double grav_G;   /* gravitational constant in code units; 0 = no self-gravity */
     double n_unit;   /* H nuclei per cm^3 per unit code density */
     double T_unit;   /* K: T = T_unit * mu * p / rho            */
@@ -364,8 +377,23 @@ void orc_riemann_face(const double cl[7], const double cr[7],
 /* Sec. 2 (equation of state, field projection of Sec. 2.5)             */
 /* ------------------------------------------------------------------ */
 
-/* primitive state of one cell: rho, vx, vy, vz, Bcx, Bcy, Bcz, p */
-static void cell_primitives(const orc_params *P, const double *U, int i, int j, int k, double w[8])
+/* Sec. 4.3: effective adiabatic index (5 n_H + 5 n_e + 7 n_H2) / (3 n_H + 3 n_e + 5 n_H2)
+ * with the ionisation network, the constant gamma without it */
+double orc_gamma_cell(const orc_params *P, double rho, double h2, double hp)
+{
+    if (!P->ionisation) return P->gamma;
+    double nH = rho - h2 - hp, nH2 = 0.5 * h2, ne = hp;   /* in units of n_u */
+    return (5.0 * nH + 5.0 * ne + 7.0 * nH2) / (3.0 * nH + 3.0 * ne + 5.0 * nH2);
+}
+
+/* mean particle mass in m_H: rho / (n_H + n_H2 + n_H+ + n_e) per unit n_u */
+static double mean_mass(double rho, double h2, double hp)
+{
+    return 1.0 / (1.0 - 0.5 * (h2 / rho) + hp / rho);
+}
+
+/* primitive state of one cell: rho, vx, vy, vz, Bcx, Bcy, Bcz, p, gamma */
+static void cell_primitives(const orc_params *P, const double *U, int i, int j, int k, double w[9])
 {
     size_t N = ncell(P);
     size_t c = cell(P, i, j, k);
@@ -377,7 +405,8 @@ static void cell_primitives(const orc_params *P, const double *U, int i, int j, 
     w[4] = 0.5 * (U[F_BX * N + c] + U[F_BX * N + cell(P, i + 1, j, k)]);
     w[5] = 0.5 * (U[F_BY * N + c] + U[F_BY * N + cell(P, i, j + 1, k)]);
     w[6] = 0.5 * (U[F_BZ * N + c] + U[F_BZ * N + cell(P, i, j, k + 1)]);
-    w[7] = (P->gamma - 1.0) * U[F_EI * N + c];
+    w[8] = orc_gamma_cell(P, rho, U[F_H2 * N + c], U[F_HP * N + c]);
+    w[7] = (w[8] - 1.0) * U[F_EI * N + c];
 }
 
 /* direction d: normal axis d, transverse t1 = d+1, t2 = d+2 (cyclic) */
@@ -400,7 +429,7 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
     const double gm = P->gamma;
     const double eps = 1e-12;
 
-    double *W = (double *)malloc(sizeof(double) * 8 * N);
+    double *W = (double *)malloc(sizeof(double) * 9 * N);
     /* face states per direction: Vn, Vt1, Vt2, Bt1, Bt2, P (6 x N per direction) */
     double *FS = (double *)malloc(sizeof(double) * 18 * N);
 
@@ -408,10 +437,10 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
             for (int i = 0; i < nx; i++) {
-                double w[8];
+                double w[9];
                 cell_primitives(P, U, i, j, k, w);
                 size_t c = cell(P, i, j, k);
-                for (int v = 0; v < 8; v++) W[v * N + c] = w[v];
+                for (int v = 0; v < 9; v++) W[v * N + c] = w[v];
             }
 
     for (int d = 0; d < 3; d++) {
@@ -424,7 +453,7 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
             for (int j = 0; j < ny; j++)
                 for (int i = 0; i < nx; i++) {
                     /* face between cell c - e_d (left) and c (right) */
-                    double line[6][7];    /* cells c-3e_d .. c+2e_d: rho, vn, vt1, vt2, Bt1, Bt2, p */
+                    double line[6][8];    /* cells c-3e_d .. c+2e_d: rho, vn, vt1, vt2, Bt1, Bt2, p, gamma */
                     for (int m = 0; m < 6; m++) {
                         int s = m - 3;
                         size_t cc = cell(P, i + s * o[0], j + s * o[1], k + s * o[2]);
@@ -435,6 +464,7 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
                         line[m][4] = W[(4 + t1) * N + cc];
                         line[m][5] = W[(4 + t2) * N + cc];
                         line[m][6] = W[7 * N + cc];
+                        line[m][7] = W[8 * N + cc];
                     }
                     double parl[24], parr[24];
                     for (int v = 0; v < 6; v++) {
@@ -448,7 +478,13 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
                     }
                     size_t c = cell(P, i, j, k);
                     double out[6];
-                    orc_riemann_face(line[2], line[3], parl, parr, bface[c], gm, eps, ydx, out);
+                    /* face adiabatic index: the sqrt(rho)-weighted mean of the two cells' */
+                    double gface = gm;
+                    if (P->ionisation) {
+                        double sl = sqrt(line[2][0]), sr = sqrt(line[3][0]);
+                        gface = (sl * line[2][7] + sr * line[3][7]) / (sl + sr);
+                    }
+                    orc_riemann_face(line[2], line[3], parl, parr, bface[c], gface, eps, ydx, out);
                     for (int v = 0; v < 6; v++) FS[(size_t)(6 * d + v) * N + c] = out[v];
                 }
     }
@@ -525,7 +561,7 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
                 }
                 inc[F_E * N + c] = -dtdx * (dF[0][3] + dF[1][3] + dF[2][3]);
                 double divv = dF[0][4] + dF[1][4] + dF[2][4];
-                inc[F_EI * N + c] = -(gm - 1.0) * U[F_EI * N + c] * dtdx * divv;
+                inc[F_EI * N + c] = -(W[8 * N + c] - 1.0) * U[F_EI * N + c] * dtdx * divv;
 
                 /* Sec. 2.5 face-field update from the edge fields */
                 double dEz_y = Ed[2 * N + cell(P, i, j + 1, k)] - Ed[2 * N + c];
@@ -539,6 +575,7 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
                 inc[F_BZ * N + c] = -dtdx * dEy_x + dtdx * dEx_y;
                 inc[F_RHO * N + c] = 0.0;
                 inc[F_H2 * N + c] = 0.0;
+                inc[F_HP * N + c] = 0.0;
             }
 
     /* Sec. 2 (momentum and energy equations) and Sec. 2.4: self-gravity
@@ -580,7 +617,7 @@ static void nonadv_increment(const orc_params *P, const double *U, double dt, do
 /* conserved fields rho, mx, my, mz, E, e, h2 with the sqrt(rho)-weighted */
 /* face velocity.                                                       */
 /* ------------------------------------------------------------------ */
-static const int adv_fields[7] = { F_RHO, F_MX, F_MY, F_MZ, F_E, F_EI, F_H2 };
+static const int adv_fields[8] = { F_RHO, F_MX, F_MY, F_MZ, F_E, F_EI, F_H2, F_HP };
 
 static void adv_increment(const orc_params *P, const double *U, double dt, double *inc)
 {
@@ -590,7 +627,8 @@ static void adv_increment(const orc_params *P, const double *U, double dt, doubl
     const double dtdx = dt / h;
     const double ydx = P->theta * dtdx;
 
-    double *F = (double *)malloc(sizeof(double) * 21 * N);   /* per dir, per field */
+    const int nadv = P->ionisation ? 8 : 7;                   /* H+ is advected with the network */
+    double *F = (double *)malloc(sizeof(double) * 24 * N);   /* per dir, per field */
 
     for (int d = 0; d < 3; d++) {
         int o[3];
@@ -606,7 +644,7 @@ static void adv_increment(const orc_params *P, const double *U, double dt, doubl
                     double vr = U[(size_t)(F_MX + d) * N + c] / rr;
                     double sl = sqrt(rl), sr = sqrt(rr);
                     double vf = (sl * vl + sr * vr) / (sl + sr);
-                    for (int f = 0; f < 7; f++) {
+                    for (int f = 0; f < nadv; f++) {
                         const double *q = U + (size_t)adv_fields[f] * N;
                         double flux;
                         if (vf >= 0.0) {
@@ -626,7 +664,7 @@ static void adv_increment(const orc_params *P, const double *U, double dt, doubl
                             orc_parabola(s5, par);
                             flux = vf * orc_avg_left(par, ydx * (-vf));
                         }
-                        F[(size_t)(7 * d + f) * N + c] = flux;
+                        F[(size_t)(8 * d + f) * N + c] = flux;
                     }
                 }
     }
@@ -637,12 +675,13 @@ static void adv_increment(const orc_params *P, const double *U, double dt, doubl
             for (int i = 0; i < nx; i++) {
                 size_t c = cell(P, i, j, k);
                 size_t up[3] = { cell(P, i + 1, j, k), cell(P, i, j + 1, k), cell(P, i, j, k + 1) };
-                for (int f = 0; f < 7; f++) {
-                    double dx = F[(size_t)(7 * 0 + f) * N + up[0]] - F[(size_t)(7 * 0 + f) * N + c];
-                    double dy = F[(size_t)(7 * 1 + f) * N + up[1]] - F[(size_t)(7 * 1 + f) * N + c];
-                    double dz = F[(size_t)(7 * 2 + f) * N + up[2]] - F[(size_t)(7 * 2 + f) * N + c];
+                for (int f = 0; f < nadv; f++) {
+                    double dx = F[(size_t)(8 * 0 + f) * N + up[0]] - F[(size_t)(8 * 0 + f) * N + c];
+                    double dy = F[(size_t)(8 * 1 + f) * N + up[1]] - F[(size_t)(8 * 1 + f) * N + c];
+                    double dz = F[(size_t)(8 * 2 + f) * N + up[2]] - F[(size_t)(8 * 2 + f) * N + c];
                     inc[(size_t)adv_fields[f] * N + c] = -dtdx * (dx + dy + dz);
                 }
+                if (nadv == 7) inc[F_HP * N + c] = 0.0;
                 inc[F_BX * N + c] = 0.0;
                 inc[F_BY * N + c] = 0.0;
                 inc[F_BZ * N + c] = 0.0;
@@ -809,6 +848,39 @@ double orc_heat_cool(const orc_params *P, double rho, double e, double h2, doubl
     return (g1 + g4) - (l2 + l3);
 }
 
+/* With the ionisation network: the cell's adiabatic index and mean mass,
+ * n_H = n_u (rho - h2 - hp), n = n_H + n_H2 + n_H+, and the terms of
+ * reactions 5 and 6 added: cosmic-ray heating Gamma5 = 1.92e-28 n and
+ * collisional-ionisation cooling Lambda6 = 2.18e-11 erg (13.6 eV) x k6 n_H n_e.
+ * The printed Lambda7 (column densities and a square root of time) and
+ * Lambda8 (no density factor) are left out.  terms_out (optional): Gamma1,
+ * Gamma4, Lambda2, Lambda3, T, Gamma5, Lambda6. */
+double orc_k6(double T);
+
+double orc_heat_cool_ion(const orc_params *P, double rho, double e, double h2, double hp, double *terms_out)
+{
+    double gam = orc_gamma_cell(P, rho, h2, hp);
+    double p = (gam - 1.0) * e;
+    double T = P->T_unit * mean_mass(rho, h2, hp) * p / rho;
+    double nH = P->n_unit * (rho - h2 - hp);
+    double nH2 = P->n_unit * h2 / 2.0;
+    double ne = P->n_unit * hp;
+    double n = nH + nH2 + ne;
+    double g1 = 7.2e-12 * (orc_k1_base(T) * n * nH) / (1.0 + orc_ncrit(T) / n);
+    double g4 = 6.4e-13 * orc_k4() * nH2;
+    double lh2 = orc_lh2(T);
+    double l2 = nH2 * lh2 / (1.0 + lh2 / orc_ll2(T, nH, nH2));
+    double ln_lh3 = log(1.1e-13) - 6744.0 / T;
+    double l3 = nH2 * exp(ln_lh3) / (1.0 + exp(ln_lh3 - orc_ln_ll3(T, n)));
+    double g5 = 1.92e-28 * n;
+    double l6 = 2.18e-11 * orc_k6(T) * nH * ne;
+    if (terms_out) {
+        terms_out[0] = g1; terms_out[1] = g4; terms_out[2] = l2; terms_out[3] = l3; terms_out[4] = T;
+        terms_out[5] = g5; terms_out[6] = l6;
+    }
+    return (g1 + g4 + g5) - (l2 + l3 + l6);
+}
+
 /* Sec. 2.8: explicit Euler step of d(rho eps)/dt = d(rho E)/dt = Gamma - Lambda
  * with the rates frozen over dt.  The code energy density unit is
  * n_u k_B T_u; cooling stops at the internal energy of T_floor (or at the
@@ -821,9 +893,16 @@ void orc_cooling(const orc_params *P, double *U, double dt)
     #pragma omp parallel for schedule(static)
     for (size_t c = 0; c < N; c++) {
         double rho = U[F_RHO * N + c], e = U[F_EI * N + c], h2 = U[F_H2 * N + c];
-        double de = dt * P->t_unit * orc_heat_cool(P, rho, e, h2, NULL) / eu;
-        double mu = 1.0 / (1.0 - 0.5 * (h2 / rho));
-        double efloor = rho * ORC_T_FLOOR / (P->T_unit * mu * (P->gamma - 1.0));
+        double de, efloor;
+        if (P->ionisation) {
+            double hp = U[F_HP * N + c];
+            de = dt * P->t_unit * orc_heat_cool_ion(P, rho, e, h2, hp, NULL) / eu;
+            efloor = rho * ORC_T_FLOOR / (P->T_unit * mean_mass(rho, h2, hp) * (orc_gamma_cell(P, rho, h2, hp) - 1.0));
+        } else {
+            de = dt * P->t_unit * orc_heat_cool(P, rho, e, h2, NULL) / eu;
+            double mu = 1.0 / (1.0 - 0.5 * (h2 / rho));
+            efloor = rho * ORC_T_FLOOR / (P->T_unit * mu * (P->gamma - 1.0));
+        }
         double lo = e < efloor ? e : efloor;
         double en = e + de;
         if (en < lo) en = lo;
@@ -911,7 +990,8 @@ void orc_potential(const orc_params *P, const double *rho, double *phi)
     free(im);
 }
 
-/* clamp of the advected H2 density to [0, rho] (total hydrogen closure) */
+/* clamp of the advected H2 density to [0, rho] and, with the ionisation
+ * network, of the H+ density to [0, rho - h2] (total hydrogen closure) */
 void orc_clamp_h2(const orc_params *P, double *U)
 {
     const size_t N = ncell(P);
@@ -920,6 +1000,92 @@ void orc_clamp_h2(const orc_params *P, double *U)
         if (x > r) x = r;
         if (x < 0.0) x = 0.0;
         U[F_H2 * N + c] = x;
+        if (P->ionisation) {
+            double y = U[F_HP * N + c];
+            if (y > r - x) y = r - x;
+            if (y < 0.0) y = 0.0;
+            U[F_HP * N + c] = y;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 4.3 + Appendix: reactions 5-8 of the ionisation network.        */
+/* ------------------------------------------------------------------ */
+
+/* reaction 5, cosmic-ray ionisation: s^-1 per H atom (the printed n_H2
+ * factor is read as a typesetting slip: Gamma5 = 1.92e-28 n is 20 eV per
+ * ionisation at this rate per atom) */
+double orc_k5(void) { return 6e-18; }
+
+/* reaction 6, collisional ionisation (cm^3 s^-1): exp of the printed
+ * polynomial in ln(T) with T in eV */
+double orc_k6(double T)
+{
+    static const double c[9] = { -32.7, 13.5, -5.7, 1.5, -0.3, 3.4e-2, -2.6e-3, 1.1e-4, -2.1e-6 };
+    double l = log(T * ORC_KB_EV), s = 0.0, lp = 1.0;
+    for (int i = 0; i < 9; i++) {
+        s += c[i] * lp;
+        lp *= l;
+    }
+    return exp(s);
+}
+
+/* reaction 7, radiative recombination (cm^3 s^-1): 10 to the printed ratio
+ * of quartics in x = log10(T) */
+double orc_k7(double T)
+{
+    double x = log10(T);
+    double num = -10.78 + 4.68 * x - 0.87 * x * x + 0.08 * x * x * x - 3.87e-3 * x * x * x * x;
+    double den = 1.0 - 0.38 * x + 0.06 * x * x - 5.1e-3 * x * x * x + 2.4e-4 * x * x * x * x;
+    return pow(10.0, num / den);
+}
+
+/* reaction 8, recombination on grains (cm^3 s^-1), as printed with log = log10 */
+double orc_k8(double T)
+{
+    double inner = 1.0 + 5.087e2 * pow(T, 1.586e-2) * pow(10.0, -1.8892 - 4.4e-5 * log10(T));
+    return 12.25e-14 / (1.0 + 8.074e-6 * pow(10.0, 2.756) * inner);
+}
+
+/* Sec. 2.7 with reactions 1-8: new H2 and H+ mass densities of one cell.
+ * n_H = n_u (rho - h2 - hp), n_H2 = n_u h2 / 2, n_e = n_H+ = n_u hp, all
+ * frozen at the start of the step; one semi-implicit update per species;
+ * H2 is clamped to [0, n_u (rho - hp) / 2], then H+ to [0, n_u (rho - h2')].
+ * rates_out (optional): k1', k2, k3, k4, k5, k6, k7, k8, T. */
+void orc_chem_cell_ion(const orc_params *P, double rho, double e, double h2, double hp, double dt, double *h2_out,
+                       double *hp_out, double *rates_out)
+{
+    double gam = orc_gamma_cell(P, rho, h2, hp);
+    double p = (gam - 1.0) * e;
+    double T = P->T_unit * mean_mass(rho, h2, hp) * p / rho;
+    double nH = P->n_unit * (rho - h2 - hp);
+    double nH2 = P->n_unit * h2 / 2.0;
+    double ne = P->n_unit * hp;
+    double n = nH + nH2 + ne;
+    double ts = dt * P->t_unit;
+    double k1b = orc_k1_base(T), k2 = orc_k2(T), k3 = orc_k3(T), k4 = orc_k4();
+    double k5 = orc_k5(), k6 = orc_k6(T), k7 = orc_k7(T), k8 = orc_k8(T);
+    /* H2 */
+    double C = k1b * n * nH;
+    double D = k2 * nH + k3 * nH2 + k4;
+    double m2 = nH2 + ts * (C - D * nH2) / (1.0 + ts * D);
+    double m2max = P->n_unit * (rho - hp) / 2.0;
+    if (m2 > m2max) m2 = m2max;
+    if (m2 < 0.0) m2 = 0.0;
+    /* H+ (= e-) */
+    double Ci = k5 * nH + k6 * nH * ne;
+    double Di = (k7 + k8) * ne;
+    double mi = ne + ts * (Ci - Di * ne) / (1.0 + ts * Di);
+    double h2n = 2.0 * m2 / P->n_unit;
+    double mimax = P->n_unit * (rho - h2n);
+    if (mi > mimax) mi = mimax;
+    if (mi < 0.0) mi = 0.0;
+    *h2_out = h2n;
+    *hp_out = mi / P->n_unit;
+    if (rates_out) {
+        rates_out[0] = k1b; rates_out[1] = k2; rates_out[2] = k3; rates_out[3] = k4;
+        rates_out[4] = k5; rates_out[5] = k6; rates_out[6] = k7; rates_out[7] = k8; rates_out[8] = T;
     }
 }
 
@@ -927,8 +1093,17 @@ void orc_chemistry(const orc_params *P, double *U, double dt)
 {
     const size_t N = ncell(P);
     #pragma omp parallel for schedule(static)
-    for (size_t c = 0; c < N; c++)
-        U[F_H2 * N + c] = orc_chem_cell(P, U[F_RHO * N + c], U[F_EI * N + c], U[F_H2 * N + c], dt, NULL);
+    for (size_t c = 0; c < N; c++) {
+        if (P->ionisation) {
+            double h2n, hpn;
+            orc_chem_cell_ion(P, U[F_RHO * N + c], U[F_EI * N + c], U[F_H2 * N + c], U[F_HP * N + c], dt, &h2n,
+                              &hpn, NULL);
+            U[F_H2 * N + c] = h2n;
+            U[F_HP * N + c] = hpn;
+        } else {
+            U[F_H2 * N + c] = orc_chem_cell(P, U[F_RHO * N + c], U[F_EI * N + c], U[F_H2 * N + c], dt, NULL);
+        }
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -951,7 +1126,8 @@ void orc_regularise(const orc_params *P, double *U)
                 double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
                 double M = 0.5 * (bx * bx + by * by + bz * bz);
                 double ei = E - K - M;
-                if (ei >= 1e-3 * E && (P->gamma - 1.0) * ei > M) U[F_EI * N + c] = ei;
+                double gam = orc_gamma_cell(P, rho, U[F_H2 * N + c], U[F_HP * N + c]);
+                if (ei >= 1e-3 * E && (gam - 1.0) * ei > M) U[F_EI * N + c] = ei;
             }
 }
 
@@ -961,11 +1137,11 @@ void orc_regularise(const orc_params *P, double *U)
 double orc_cell_speed(const orc_params *P, const double *U, int i, int j, int k)
 {
     const size_t N = ncell(P);
-    double w[8];
+    double w[9];
     cell_primitives(P, U, i, j, k, w);
     double rho = w[0];
     double v = sqrt(w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
-    double c2 = P->gamma * w[7] / rho;
+    double c2 = w[8] * w[7] / rho;
     double ca2 = w[4] * w[4] / rho;
     double b2 = (w[4] * w[4] + w[5] * w[5] + w[6] * w[6]) / rho;
     double s = c2 + b2;
@@ -1025,7 +1201,7 @@ void orc_totals(const orc_params *P, const double *U, double out[NF])
     }
 }
 
-/* primitive -> conserved: prim fields rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2 */
+/* primitive -> conserved: prim fields rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2, x_hp */
 void orc_prim_to_cons(const orc_params *P, const double *W, double *U)
 {
     const size_t N = ncell(P);
@@ -1039,7 +1215,8 @@ void orc_prim_to_cons(const orc_params *P, const double *W, double *U)
                 double bx = 0.5 * (W[5 * N + c] + W[5 * N + cell(P, i + 1, j, k)]);
                 double by = 0.5 * (W[6 * N + c] + W[6 * N + cell(P, i, j + 1, k)]);
                 double bz = 0.5 * (W[7 * N + c] + W[7 * N + cell(P, i, j, k + 1)]);
-                double e = p / (P->gamma - 1.0);
+                double h2 = W[8 * N + c] * rho, hp = W[9 * N + c] * rho;
+                double e = p / (orc_gamma_cell(P, rho, h2, hp) - 1.0);
                 U[F_RHO * N + c] = rho;
                 U[F_MX * N + c] = rho * vx;
                 U[F_MY * N + c] = rho * vy;
@@ -1049,7 +1226,8 @@ void orc_prim_to_cons(const orc_params *P, const double *W, double *U)
                 U[F_BX * N + c] = W[5 * N + c];
                 U[F_BY * N + c] = W[6 * N + c];
                 U[F_BZ * N + c] = W[7 * N + c];
-                U[F_H2 * N + c] = W[8 * N + c] * rho;
+                U[F_H2 * N + c] = h2;
+                U[F_HP * N + c] = hp;
             }
 }
 

@@ -3,13 +3,14 @@
 This module holds no arithmetic of the numerical method: it only draws and
 shapes initial data.  Both the HIP path and the CPU oracle consume its output.
 
-Every generator returns a float64 array ``W`` of shape (9, nz, ny, nx) with the
+Every generator returns a float64 array ``W`` of shape (10, nz, ny, nx) with the
 primitive fields, x fastest in memory:
 
-    rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2
+    rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2, x_hp
 
 where ``bx_f[k, j, i]`` is B_x on the lower x face (i-1/2, j, k) of the cell
-(and likewise for y and z), and ``x_h2`` is the H2 mass fraction.  Units are
+(and likewise for y and z), ``x_h2`` is the H2 mass fraction and ``x_hp`` the H+ mass fraction (zero
+unless a generator is asked for ionised gas).  Units are
 Heaviside-Lorentz (B^2/2 is the magnetic pressure), the box is the periodic
 unit cube with cubic cells of edge h = 1/nx.
 
@@ -22,12 +23,12 @@ plasma beta = 2 p0 / B0^2; pressure is isothermal p = p0 rho / rho0.
 """
 import numpy as np
 
-PRIM = ("rho", "vx", "vy", "vz", "p", "bx_f", "by_f", "bz_f", "x_h2")
+PRIM = ("rho", "vx", "vy", "vz", "p", "bx_f", "by_f", "bz_f", "x_h2", "x_hp")
 
 
 def _alloc(shape):
     nz, ny, nx = shape
-    return np.zeros((9, nz, ny, nx), dtype=np.float64)
+    return np.zeros((10, nz, ny, nx), dtype=np.float64)
 
 
 def uniform(shape, rho=1.0, v=(0.0, 0.0, 0.0), p=1.0, B=(0.0, 0.0, 0.0), x_h2=1e-3):

@@ -35,7 +35,7 @@ def _warm_molecular_state(shape, seed):
     fractions up to 0.5, so every heating and cooling term and both branches of
     the Lambda2 fits are exercised."""
     rng = np.random.default_rng(seed)
-    W = np.zeros((9,) + shape)
+    W = np.zeros((10,) + shape)
     W[0] = rng.uniform(0.5, 2.0, shape)
     W[1:4] = rng.normal(0, 0.3, (3,) + shape)
     W[4] = rng.uniform(0.05, 3.0, shape)

@@ -108,7 +108,7 @@ def _state(seed, n=6):
     rng = np.random.default_rng(seed)
     shape = (n, n, n)
     P = oracle.make_params(shape, cooling=True)
-    W = np.zeros((9,) + shape)
+    W = np.zeros((10,) + shape)
     W[0] = rng.uniform(0.5, 2.0, shape)
     W[1:4] = rng.normal(0, 0.3, (3,) + shape)
     W[4] = rng.uniform(0.05, 3.0, shape)          # T from about 150 K to 9000 K
@@ -147,7 +147,7 @@ def test_temperature_change_in_cgs():
     P = _P(shape=(1, 1, 1))
     rho, h2 = 1.3, 0.26
     e = _e_at(P, 2500.0, rho, h2)
-    U = np.zeros((10, 1, 1, 1))
+    U = np.zeros((oracle.NF, 1, 1, 1))
     U[0], U[4], U[5], U[9] = rho, e, e, h2
     r, t = oracle.heat_cool(P, rho, e, h2)
     tau = 1e-6      # far from the floor: the cooling time of this cell is about 1e-4
@@ -162,7 +162,7 @@ def test_temperature_change_in_cgs():
 def test_strong_cooling_stops_at_10K():
     P = _P(n_unit=5e4, shape=(1, 1, 1))
     rho, h2 = 1.0, 0.5
-    U = np.zeros((10, 1, 1, 1))
+    U = np.zeros((oracle.NF, 1, 1, 1))
     e = _e_at(P, 3000.0, rho, h2)
     U[0], U[4], U[5], U[9] = rho, e + 7.0, e, h2
     r, _ = oracle.heat_cool(P, rho, e, h2)

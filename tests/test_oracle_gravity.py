@@ -75,7 +75,7 @@ def test_potential_translates_with_density():
 
 def _state(shape, seed):
     rng = np.random.default_rng(seed)
-    W = np.zeros((9,) + shape)
+    W = np.zeros((10,) + shape)
     W[0] = rng.uniform(0.5, 2.0, shape)
     W[1:4] = rng.normal(0, 0.3, (3,) + shape)
     W[4] = rng.uniform(0.5, 1.5, shape)
@@ -111,7 +111,7 @@ def test_gravity_pulls_towards_density_peak():
     n = 32
     shape = (1, 1, n)
     x = (np.arange(n) + 0.5) / n
-    W = np.zeros((9,) + shape)
+    W = np.zeros((10,) + shape)
     W[0] = (1.0 + 0.1 * np.cos(2 * np.pi * x)).reshape(shape)
     W[4] = 1.0          # uniform pressure: no pressure force
     P = oracle.make_params(shape, grav_G=1.0, chemistry=False)

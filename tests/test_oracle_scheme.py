@@ -58,7 +58,7 @@ def test_conservation_periodic_box():
     t0 = fsum_fields(U)
     oracle.run(P, U, 10)
     t1 = fsum_fields(U)
-    absq = np.abs(U).reshape(10, -1).sum(axis=1)
+    absq = np.abs(U).reshape(oracle.NF, -1).sum(axis=1)
     for f in (0, 1, 2, 3, 4, 6, 7, 8):
         assert abs(t1[f] - t0[f]) / absq[f] <= 1e-13, oracle.FIELDS[f]
     # the oracle's own compensated totals agree with exact summation
@@ -109,7 +109,7 @@ def test_cyclic_permutation_commutes():
         oracle.step(P, U, dt)
         oracle.step(P, V, dt)
     R = rot(U)
-    scale = np.abs(R).reshape(10, -1).max(axis=1)[:, None, None, None]
+    scale = np.abs(R).reshape(oracle.NF, -1).max(axis=1)[:, None, None, None]
     assert np.abs(R - V).max() / 1.0 <= 1e-12 * max(1.0, float(scale.max()))
 
 
