@@ -62,6 +62,12 @@ enum {
 
 enum { MHD_FP64 = 0, MHD_FP32_MIXED = 1 };
 
+/* Conserved fields of the state (host order): rho, mx, my, mz, E, e (= rho eps),
+ * bx, by, bz (face values), h2 (= rho_H2), hp (= rho_H+, zero and untouched
+ * unless the ionisation network is on); primitive fields for mhd_init_state:
+ * rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2, x_hp. */
+enum { MHD_NFIELDS = 11, MHD_NPRIM = 10 };
+
 /* Stage selectors of mhd_debug_stage. */
 enum {
     MHD_STAGE_NONADV = 1,    /* the NONADV Runge-Kutta stage only                   */
@@ -87,6 +93,12 @@ typedef struct {
                              /* d(rho eps)/dt = d(rho E)/dt = Gamma - Lambda with the     */
                              /* appendix heating/cooling of reactions 1-4, FP64, energy  */
                              /* unit n_unit k_B T_unit, floor at 10 K                     */
+    int32_t ionisation;      /* 0 or 1: ionisation network (Sec. 4.3, reactions 5-8):  */
+                             /* H+ density advected as the 11th field, n_e = n_H+, its   */
+                             /* semi-implicit update with chemistry, cosmic-ray heating  */
+                             /* and collisional-ionisation cooling with heating/cooling, */
+                             /* and gamma_eff = (5 n_H + 5 n_e + 7 n_H2) /               */
+                             /* (3 n_H + 3 n_e + 5 n_H2) per cell in place of gamma      */
     double grav_G;           /* self-gravity (Sec. 2 equations, Sec. 2.9): gravitational  */
                              /* constant in code units, 0 = off.  When > 0 every step     */
                              /* solves Laplace(Phi) = 4 pi G rho with the 27-point        */
@@ -113,19 +125,20 @@ size_t mhd_workspace_bytes(const mhd_params *p);
  * Host-only (no device call).  *out is owned by the caller until mhd_destroy. */
 int mhd_create(const mhd_params *p, mhd_box **out);
 
-/* Load a primitive state: host FP64, 9 fields of n[0]*n[1]*n[2] values, order
- * rho, vx, vy, vz, p, bx_face, by_face, bz_face, x_h2 (H2 mass fraction).
- * Converts to conserved form on the device (Sec. 2: rho E = e + rho v^2/2 +
- * B^2/2 with cell-centre B the mean of the two faces, p = (gamma-1) e),
+/* Load a primitive state: host FP64, MHD_NPRIM = 10 fields of n[0]*n[1]*n[2]
+ * values, order rho, vx, vy, vz, p, bx_face, by_face, bz_face, x_h2, x_hp (H2
+ * and H+ mass fractions).  Converts to conserved form on the device (Sec. 2:
+ * rho E = e + rho v^2/2 + B^2/2 with cell-centre B the mean of the two faces,
+ * p = (gamma-1) e, gamma_eff of the cell with the ionisation network),
  * computes the first CFL step, clears latched faults.  Synchronises. */
 int mhd_init_state(mhd_box *b, const double *prim);
 
-/* Load a conserved state (host FP64, the 10 fields above); clears faults and
+/* Load a conserved state (host FP64, the MHD_NFIELDS fields above); clears faults and
  * recomputes the CFL step.  Synchronises.  With mhd_get_state this is the
  * checkpoint / resume pair (bitwise for MHD_FP64). */
 int mhd_set_state(mhd_box *b, const double *cons);
 
-/* Copy the current conserved state to host FP64 (10 fields).  Synchronises;
+/* Copy the current conserved state to host FP64 (MHD_NFIELDS fields).  Synchronises;
  * returns a latched fault if any. */
 int mhd_get_state(mhd_box *b, double *cons_out);
 
@@ -152,10 +165,10 @@ int mhd_step(mhd_box *b, double dt);
  * (no host round trip). */
 int mhd_step_cfl(mhd_box *b);
 
-/* FP64 sums over all cells of the 10 conserved fields (field order above;
+/* FP64 sums over all cells of the MHD_NFIELDS conserved fields (field order above;
  * the face fields sum their face values).  Fixed-order tree reduction:
  * repeatable bit for bit.  Synchronises; returns a latched fault if any. */
-int mhd_conserved_totals(mhd_box *b, double out[10]);
+int mhd_conserved_totals(mhd_box *b, double out[MHD_NFIELDS]);
 
 /* Run one part of the step on the current state (stage selectors above),
  * for per-stage parity checks.  Asynchronous. */
@@ -226,7 +239,7 @@ typedef struct {
     int32_t status;          /* MHD_OK or the box's latched fault                */
     int32_t steps;           /* steps run                                         */
     double t_submit, t_admit, t_done;   /* seconds since mhd_server_create       */
-    double totals[10];       /* conserved totals of the final state (FP64)      */
+    double totals[MHD_NFIELDS]; /* conserved totals of the final state (FP64)   */
     int64_t cells;
     size_t bytes;            /* workspace bytes the box held                     */
 } mhd_completion;
@@ -257,7 +270,7 @@ int mhd_server_progress(mhd_server *s, int *n_active, int *n_pending);
 /* Take up to cap completion records (oldest first). */
 int mhd_server_poll(mhd_server *s, mhd_completion *out, int cap, int *n);
 
-/* Copy the final conserved state (10 fields, host FP64) of a finished request
+/* Copy the final conserved state (MHD_NFIELDS fields, host FP64) of a finished request
  * submitted with keep_state = 1; count must be 10 * cells.  Once per request. */
 int mhd_server_result(mhd_server *s, uint64_t id, double *cons_out, size_t count);
 

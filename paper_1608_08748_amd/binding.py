@@ -17,7 +17,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mhdchem.h")
 MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ECFL, MHD_ENONPHYS = 0, -1, -2, -3, -4, -5
 FP64, FP32_MIXED = 0, 1
 STAGE_NONADV, STAGE_ADV, STAGE_TAIL, STAGE_NONADV_RHS, STAGE_ADV_RHS = 1, 2, 3, 4, 5
-FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2")
+FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2", "hp")
+NFIELDS = len(FIELDS)      # conserved fields (hp = rho_H+, zero without the ionisation network)
+NPRIM = 10                 # primitive fields: rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2, x_hp
 KCLASSES = ("prim", "nonadv_face", "nonadv_update", "adv_face", "adv_update", "tail", "reduce", "poisson")
 NKCLASS = len(KCLASSES)
 
@@ -36,6 +38,7 @@ class MhdParams(ctypes.Structure):
         ("theta", ctypes.c_double),
         ("chemistry", ctypes.c_int32),
         ("cooling", ctypes.c_int32),
+        ("ionisation", ctypes.c_int32),
         ("grav_G", ctypes.c_double),
         ("n_unit_cm3", ctypes.c_double),
         ("T_unit_K", ctypes.c_double),
@@ -76,7 +79,7 @@ class Completion(ctypes.Structure):
         ("t_submit", ctypes.c_double),
         ("t_admit", ctypes.c_double),
         ("t_done", ctypes.c_double),
-        ("totals", ctypes.c_double * 10),
+        ("totals", ctypes.c_double * NFIELDS),
         ("cells", ctypes.c_int64),
         ("bytes", ctypes.c_size_t),
     ]
@@ -161,7 +164,7 @@ def gravity_G(units=None):
 
 
 def make_params(shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None,
-                cooling=False, grav_G=0.0):
+                cooling=False, grav_G=0.0, ionisation=False):
     nz, ny, nx = shape
     p = MhdParams()
     p.n[0], p.n[1], p.n[2] = nx, ny, nz
@@ -169,6 +172,7 @@ def make_params(shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chem
     p.chemistry = 1 if chemistry else 0
     p.cooling = 1 if cooling else 0
     p.grav_G = float(grav_G)
+    p.ionisation = 1 if ionisation else 0
     p.n_unit_cm3, p.T_unit_K, p.t_unit_s = units if units is not None else DEFAULT_UNITS
     return p
 
@@ -181,10 +185,11 @@ class Box:
     """One periodic box on one GPU.  shape = (nz, ny, nx)."""
 
     def __init__(self, shape, precision=FP64, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True,
-                 units=None, device="cuda", stream=None, workspace=None, cooling=False, grav_G=0.0):
+                 units=None, device="cuda", stream=None, workspace=None, cooling=False, grav_G=0.0,
+                 ionisation=False):
         import torch
         self.shape = tuple(int(s) for s in shape)
-        self.p = make_params(self.shape, precision, gamma, cfl, theta, chemistry, units, cooling, grav_G)
+        self.p = make_params(self.shape, precision, gamma, cfl, theta, chemistry, units, cooling, grav_G, ionisation)
         nbytes = workspace_bytes(self.p)
         if nbytes == 0:
             raise MhdError(MHD_EINVAL, "mhd_workspace_bytes")
@@ -205,16 +210,16 @@ class Box:
 
     def init_state(self, W):
         W = np.ascontiguousarray(W, dtype=np.float64)
-        assert W.shape == (9,) + self.shape
+        assert W.shape == (NPRIM,) + self.shape
         _check(lib().mhd_init_state(self.h, W.ctypes.data_as(_D)), "mhd_init_state")
 
     def set_state(self, U):
         U = np.ascontiguousarray(U, dtype=np.float64)
-        assert U.shape == (10,) + self.shape
+        assert U.shape == (NFIELDS,) + self.shape
         _check(lib().mhd_set_state(self.h, U.ctypes.data_as(_D)), "mhd_set_state")
 
     def get_state(self):
-        U = np.empty((10,) + self.shape, dtype=np.float64)
+        U = np.empty((NFIELDS,) + self.shape, dtype=np.float64)
         _check(lib().mhd_get_state(self.h, U.ctypes.data_as(_D)), "mhd_get_state")
         return U
 
@@ -236,7 +241,7 @@ class Box:
         _check(lib().mhd_step_cfl(self.h), "mhd_step_cfl")
 
     def totals(self):
-        out = np.zeros(10, dtype=np.float64)
+        out = np.zeros(NFIELDS, dtype=np.float64)
         _check(lib().mhd_conserved_totals(self.h, out.ctypes.data_as(_D)), "mhd_conserved_totals")
         return out
 
@@ -344,7 +349,7 @@ class Server:
 
     def result(self, rid):
         shape = self.shapes[rid]
-        U = np.empty((10,) + shape, dtype=np.float64)
+        U = np.empty((NFIELDS,) + shape, dtype=np.float64)
         _check(lib().mhd_server_result(self.h, ctypes.c_uint64(rid), U.ctypes.data_as(_D), U.size),
                "mhd_server_result")
         return U

@@ -32,6 +32,8 @@
 #include "mhd_kernels.hpp"
 #include "mhdchem.h"
 
+static_assert(mhd::NF == MHD_NFIELDS, "conserved field count of the kernels and the C ABI");
+
 using namespace mhd;
 
 // ---------------------------------------------------------------- box
@@ -43,9 +45,9 @@ struct mhd_box {
     int prec;          // MHD_FP64 / MHD_FP32_MIXED
     size_t esz;        // bytes per stored value
     int nblocks;       // cell-parallel blocks of NTH threads
-    char* slot[3];     // three Runge-Kutta copies of the 10 fields
-    char* W;           // primitives, 8 x N
-    char* F[3];        // per-direction face outputs, 7 x N each
+    char* slot[3];     // three Runge-Kutta copies of the NF fields
+    char* W;           // primitives, 8 x N (9 x N with gamma_eff)
+    char* F[3];        // per-direction face outputs, 7 x N each (8 x N with the ionisation network)
     double* part;      // per-block partials: NF x nblocks
     uint32_t* flags;
     double* dt_dev;
@@ -70,7 +72,7 @@ namespace {
 enum { GH = 0, GM = 1, GB = 2 };
 int group_of(int f)
 {
-    if (f == RHO || f == H2) return GH;
+    if (f == RHO || f == H2 || f == HP) return GH;
     if (f >= BX && f <= BZ) return GB;
     return GM;
 }
@@ -110,6 +112,8 @@ bool valid_dims(const int32_t n[3])
 bool valid_params(const mhd_params* p)
 {
     if (!p || !valid_dims(p->n)) return false;
+    if (p->ionisation != 0 && p->ionisation != 1) return false;
+    if (p->ionisation && !(p->n_unit_cm3 > 0.0 && p->T_unit_K > 0.0 && p->t_unit_s > 0.0)) return false;
     if (!(p->grav_G >= 0.0) || !std::isfinite(p->grav_G)) return false;
     if (p->grav_G > 0.0)
         for (int d = 0; d < 3; d++)
@@ -118,17 +122,21 @@ bool valid_params(const mhd_params* p)
                          p->T_unit_K, p->t_unit_s);
 }
 
-Layout layout_of(const int32_t n[3], int precision, bool grav)
+// face outputs per direction: 7 NONADV values, or 8 ADV fluxes with the
+// ionisation network
+size_t face_values(bool ion) { return ion ? NFACE + 1 : NFACE; }
+
+Layout layout_of(const int32_t n[3], int precision, bool grav, bool ion)
 {
     Layout L;
     size_t N = (size_t)n[0] * n[1] * n[2];
     size_t esz = precision == MHD_FP64 ? 8 : 4;
     size_t nb = (N + NTH - 1) / NTH;
     L.slot = align256(NF * N * esz);
-    L.W = align256(8 * N * esz);
-    size_t fbytes = align256(NFACE * N * esz);
-    // the face scratch doubles as host staging (9 or 10 FP64 fields)
-    size_t stage = align256(10 * N * 8);
+    L.W = align256((ion ? 9 : 8) * N * esz);   // + gamma_eff with the ionisation network
+    size_t fbytes = align256(face_values(ion) * N * esz);
+    // the face scratch doubles as host staging (MHD_NPRIM or NF FP64 fields)
+    size_t stage = align256((size_t)NF * N * 8);
     L.F = 3 * fbytes > stage ? 3 * fbytes : stage;
     L.part = align256(nb * NF * sizeof(double));
     L.misc = 3 * 256;
@@ -162,7 +170,7 @@ void box_bind(mhd_box* b, const mhd_params* p, const Layout& L)
     }
     b->W = w;
     w += L.W;
-    size_t fbytes = align256(NFACE * (size_t)b->g.n * b->esz);
+    size_t fbytes = align256(face_values(p->ionisation != 0) * (size_t)b->g.n * b->esz);
     for (int d = 0; d < 3; d++) b->F[d] = w + d * fbytes;
     w += L.F;
     b->part = reinterpret_cast<double*>(w);
@@ -205,6 +213,9 @@ Fields<T> view(mhd_box* b, int sH, int sM, int sB)
     for (int f = 0; f < NF; f++) {
         int grp = group_of(f);
         int s = grp == GH ? sH : (grp == GM ? sM : sB);
+        // without the ionisation network no kernel writes H+: it stays in
+        // slot 0, where the state was loaded, whatever slot is current
+        if (f == HP && !b->p.ionisation) s = 0;
         v.f[f] = reinterpret_cast<T*>(b->slot[s]) + f * N;
     }
     return v;
@@ -230,6 +241,7 @@ StepArgs step_args(mhd_box* b, double dt, bool dev)
     a.theta = b->p.theta;
     // the bound is computed from the stored state: FP32 storage moves it by ~1e-7
     a.cfl_tol = b->prec == MHD_FP64 ? 1e-12 : 1e-4;
+    a.ion = b->p.ionisation;
     return a;
 }
 
@@ -238,6 +250,7 @@ ChemArgs chem_args(mhd_box* b)
     ChemArgs c;
     c.on = b->p.chemistry;
     c.cool = b->p.cooling;
+    c.ion = b->p.ionisation;
     c.n_unit = b->p.n_unit_cm3;
     c.T_unit = b->p.T_unit_K;
     c.t_unit = b->p.t_unit_s;
@@ -448,6 +461,7 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
     ua.dbg = dbg;
     ua.zt = ztile_of(b->g);
     ua.phi = b->grav ? reinterpret_cast<const T*>(b->phi) : nullptr;
+    ua.gam = b->p.ionisation ? W + (size_t)8 * b->g.n : nullptr;
     e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
 }
 
@@ -484,7 +498,10 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     ua.zt = ztile_of(b->g);
     const int blocks = ztile_blocks(b->g, ua.zt);
     e.template launch<BAdvZUpdate<T, 0, 4>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // rho, m
-    e.template launch<BAdvZUpdate<T, 4, 3>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2
+    if (b->p.ionisation)
+        e.template launch<BAdvZUpdate<T, 4, 4>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2, hp
+    else
+        e.template launch<BAdvZUpdate<T, 4, 3>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2
 }
 
 // NONADV stage: the M and B groups each rotate through their three slots
@@ -661,7 +678,7 @@ int load_f64(mhd_box* b, const double* host, bool prim)
 {
     size_t N = (size_t)b->g.n;
     double* stage = reinterpret_cast<double*>(b->F[0]);
-    size_t nf = prim ? 9 : 10;
+    size_t nf = prim ? MHD_NPRIM : NF;
     if (hipMemcpyAsync(stage, host, nf * N * sizeof(double), hipMemcpyHostToDevice, b->s) != hipSuccess)
         return MHD_EDEVICE;
     std::vector<double> tables;
@@ -678,6 +695,7 @@ int load_f64(mhd_box* b, const double* host, bool prim)
         ia.Wp = stage;
         ia.U = u;
         ia.gamma = b->p.gamma;
+        ia.ion = b->p.ionisation;
         e.template launch<BInit<T>>(0, b->nblocks, 0, ia);
     } else {
         typename BFromF64<T>::Args ia;
@@ -863,6 +881,7 @@ mhd_params box_params(const mhd_server* sv, const int32_t n[3], void* ws, size_t
     bp.chemistry = sv->p.chemistry;
     bp.cooling = sv->p.cooling;
     bp.grav_G = 0.0;   // served boxes run without self-gravity
+    bp.ionisation = 0; // and without the ionisation network
     bp.n_unit_cm3 = sv->p.n_unit_cm3;
     bp.T_unit_K = sv->p.T_unit_K;
     bp.t_unit_s = sv->p.t_unit_s;
@@ -876,7 +895,7 @@ int server_admit(mhd_server* sv)
 {
     while (!sv->pending.empty() && (int)sv->active.size() < sv->p.max_slots) {
         mhd_server::Pending& q = sv->pending.front();
-        Layout L = layout_of(q.r.n, sv->p.precision, false);
+        Layout L = layout_of(q.r.n, sv->p.precision, false, false);
         size_t off;
         if (!pool_alloc(sv, L.total, &off)) break;   // first come, first served: wait for memory
         mhd_box* b = new (std::nothrow) mhd_box;
@@ -1000,7 +1019,7 @@ extern "C" {
 size_t mhd_workspace_bytes(const mhd_params* p)
 {
     if (!valid_params(p)) return 0;
-    return layout_of(p->n, p->precision, p->grav_G > 0.0).total;
+    return layout_of(p->n, p->precision, p->grav_G > 0.0, p->ionisation != 0).total;
 }
 
 int mhd_create(const mhd_params* p, mhd_box** out)
@@ -1008,7 +1027,7 @@ int mhd_create(const mhd_params* p, mhd_box** out)
     if (!out) return MHD_EINVAL;
     *out = nullptr;
     if (!valid_params(p)) return MHD_EINVAL;
-    Layout L = layout_of(p->n, p->precision, p->grav_G > 0.0);
+    Layout L = layout_of(p->n, p->precision, p->grav_G > 0.0, p->ionisation != 0);
     if (!p->workspace || p->workspace_bytes < L.total) return MHD_ENOMEM;
     if (((uintptr_t)p->workspace) & 255) return MHD_EINVAL;
     mhd_box* b = new (std::nothrow) mhd_box;
@@ -1105,7 +1124,7 @@ int mhd_step_cfl(mhd_box* b)
     return b->prec == MHD_FP64 ? full_step<double>(b, 0.0, true) : full_step<float>(b, 0.0, true);
 }
 
-int mhd_conserved_totals(mhd_box* b, double out[10])
+int mhd_conserved_totals(mhd_box* b, double out[MHD_NFIELDS])
 {
     if (!b || !out) return MHD_EINVAL;
     return b->prec == MHD_FP64 ? totals<double>(b, out) : totals<float>(b, out);
@@ -1146,7 +1165,7 @@ size_t mhd_server_box_bytes(const mhd_server_params* p, const int32_t n[3])
 {
     if (!p || !n || !valid_dims(n)) return 0;
     if (p->precision != MHD_FP64 && p->precision != MHD_FP32_MIXED) return 0;
-    return align256(layout_of(n, p->precision, false).total);
+    return align256(layout_of(n, p->precision, false, false).total);
 }
 
 int mhd_server_create(const mhd_server_params* p, mhd_server** out)
@@ -1185,12 +1204,12 @@ int mhd_server_submit(mhd_server* sv, const mhd_request* r, const double* prim, 
     if (!sv || !r || !prim || !id) return MHD_EINVAL;
     if (!valid_dims(r->n) || r->steps < 1) return MHD_EINVAL;
     if (r->n[0] > SERVER_MAX_NX) return MHD_EINVAL;
-    if (align256(layout_of(r->n, sv->p.precision, false).total) > sv->pool_bytes) return MHD_ENOMEM;
+    if (align256(layout_of(r->n, sv->p.precision, false, false).total) > sv->pool_bytes) return MHD_ENOMEM;
     mhd_server::Pending q;
     q.id = sv->next_id++;
     q.r = *r;
     size_t n = (size_t)r->n[0] * r->n[1] * r->n[2];
-    q.prim.assign(prim, prim + 9 * n);
+    q.prim.assign(prim, prim + (size_t)MHD_NPRIM * n);
     q.t_submit = now_s() - sv->t0;
     sv->pending.push_back(std::move(q));
     *id = sv->pending.back().id;

@@ -16,6 +16,7 @@ struct StepArgs {
     double h;               // 1 / nx
     double theta;
     double cfl_tol;         // relative slack of the dt <= CFL-bound check
+    int ion;                // ionisation network: per-cell gamma_eff (primitive slot 8)
 };
 
 __device__ __forceinline__ double step_dt(const StepArgs& a)
@@ -128,7 +129,13 @@ struct BPrim {
         W[4 * N + c] = T(0.5) * (A.U.f[BX][c] + A.U.f[BX][nbr<0>(g, c, i, j, k, 1)]);
         W[5 * N + c] = T(0.5) * (A.U.f[BY][c] + A.U.f[BY][nbr<1>(g, c, i, j, k, 1)]);
         W[6 * N + c] = T(0.5) * (A.U.f[BZ][c] + A.U.f[BZ][nbr<2>(g, c, i, j, k, 1)]);
-        W[7 * N + c] = T(A.a.gamma - 1.0) * A.U.f[EI][c];
+        if (A.a.ion) {
+            double gam = gamma_cell(1, 0.0, (double)rho, (double)A.U.f[H2][c], (double)A.U.f[HP][c]);
+            W[8 * N + c] = T(gam);
+            W[7 * N + c] = T(gam - 1.0) * A.U.f[EI][c];
+        } else {
+            W[7 * N + c] = T(A.a.gamma - 1.0) * A.U.f[EI][c];
+        }
     }
 };
 
@@ -187,10 +194,12 @@ struct BFacePair {
             side_right(PR, R, v);
         }
         T out[7];
+        const T gm = T(A.a.gamma);
+        const bool ion = A.a.ion != 0;
         face_solve(W[idx[2]], W[7 * N + idx[2]], W[(size_t)V::f[3] * N + idx[2]], W[(size_t)V::f[4] * N + idx[2]],
                    W[idx[3]], W[7 * N + idx[3]], W[(size_t)V::f[3] * N + idx[3]],
-                   W[(size_t)V::f[4] * N + idx[3]], A.bface[c], L, R, T(A.a.gamma),
-                   T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+                   W[(size_t)V::f[4] * N + idx[3]], A.bface[c], L, R, gm, ion ? W[8 * N + idx[2]] : gm,
+                   ion ? W[8 * N + idx[3]] : gm, ion, T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
         store_face(A.F, N, c, out);
     }
 };
@@ -229,6 +238,9 @@ struct BFaceXRows {
         // fields of the face solve are line values q1, q2)
         T q0[6], q1[6], q2[6], q3[6], q4[6], dm[6], fl[6];
         T rl = T(0), rr = T(0), bn = T(0);
+        const T gm = T(A.a.gamma);
+        const bool ion = A.a.ion != 0;
+        T gl = gm, gr = gm;
         const int im2 = wrapc(i - 2, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
         // slopes of the own cell
         if (act) {
@@ -244,6 +256,10 @@ struct BFaceXRows {
             rl = W[rowbase + il];
             rr = W[rowbase + i];
             bn = A.bface[rowbase + i];
+            if (ion) {
+                gl = W[8 * N + rowbase + il];
+                gr = W[8 * N + rowbase + i];
+            }
 #pragma unroll
             for (int v = 0; v < 6; v++) {
                 dm[v] = limited_slope(q1[v], q2[v], q3[v]);
@@ -291,7 +307,7 @@ struct BFaceXRows {
         }
         T out[7];
         // parabola variables 3, 4, 5 are Bt1, Bt2, p
-        face_solve(rl, q1[5], q1[3], q1[4], rr, q2[5], q2[3], q2[4], bn, L, R, T(A.a.gamma),
+        face_solve(rl, q1[5], q1[3], q1[4], rr, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gr, ion,
                    T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
         store_face(A.F, N, rowbase + i, out);
     }
@@ -357,6 +373,9 @@ struct BFaceMarch {
             fl[v] = f1;
         }
 
+        // gamma_eff of the face's left cell, carried along the march
+        const bool ion = A.a.ion != 0;
+        T gl = ion ? W[8 * N + base + wrapc(x0 - 1, nd) * stride] : gm;
         for (int x = x0; x < x1; x++) {
             int cn = base + wrapc(x + 2, nd) * stride;
 #pragma unroll
@@ -365,6 +384,7 @@ struct BFaceMarch {
                 for (int m = 0; m < 4; m++) w[v][m] = w[v][m + 1];
                 w[v][4] = W[(size_t)(v < 6 ? V::f[v] : 0) * N + cn];
             }
+            const T gr = ion ? W[8 * N + base + x * stride] : gm;
             Side<T> R, Ln;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
@@ -381,9 +401,10 @@ struct BFaceMarch {
             T out[7];
             // left cell x-1 is window slot 1, right cell x is slot 2
             face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], A.bface[c], L, R,
-                       gm, ydx, out);
+                       gm, gl, gr, ion, ydx, out);
             store_face(A.F, N, c, out);
             L = Ln;
+            gl = gr;
         }
     }
 };
@@ -410,6 +431,7 @@ struct BNonadvUpdate {
         int dbg;
         ZTile zt;
         const T* phi;   // gravitational potential, or null without self-gravity
+        const T* gam;   // per-cell gamma_eff (ionisation network), or null
     };
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -474,7 +496,7 @@ struct BNonadvUpdate {
             inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
             inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
             T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
-            inc[EI] = -T(A.a.gamma - 1.0) * A.U.f[EI][c] * dtdx * divv;
+            inc[EI] = -(A.gam ? A.gam[c] - T(1) : T(A.a.gamma - 1.0)) * A.U.f[EI][c] * dtdx * divv;
 
             T Ex_yp = Ex(yp, c, yp + dzm);
             T Ex_zp = Ex(zp, zp + dym, c);
@@ -508,6 +530,7 @@ struct BNonadvUpdate {
                 for (int q = 0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
                 A.O.f[RHO][c] = T(0);
                 A.O.f[H2][c] = T(0);
+                if (A.gam) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
             } else {
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
@@ -743,8 +766,9 @@ struct BFftYZ {
 
 // ---------------------------------------------------------------- ADV
 
-// ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, 7 x N,
-// in the order rho, mx, my, mz, E, e, h2.
+// ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, 7 x N
+// (8 x N with the ionisation network), in the order rho, mx, my, mz, E, e, h2,
+// hp.
 template <typename T, int D>
 struct BAdvFace {
     static constexpr int NT = NTH;
@@ -773,9 +797,12 @@ struct BAdvFace {
         T vf = (A.U.f[MX + D][idx[2]] * rsl + A.U.f[MX + D][c] * rsr) * rcp_nr(rl * rsl + rr * rsr);
         bool upw = vf >= T(0);
         T y = upw ? ydx * vf : ydx * (-vf);
-        const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
+        // the ionisation network advects H+ as an eighth field
+        const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
+        const int nq = A.a.ion ? 8 : 7;
 #pragma unroll
-        for (int q = 0; q < 7; q++) {
+        for (int q = 0; q < 8; q++) {
+            if (q >= nq) break;
             const T* u = A.U.f[fld[q]];
             int o = upw ? 0 : 1;
             T q0 = u[idx[o]], q1 = u[idx[o + 1]], q2 = u[idx[o + 2]], q3 = u[idx[o + 3]], q4 = u[idx[o + 4]];
@@ -787,7 +814,7 @@ struct BAdvFace {
 };
 
 // ADV z faces fused with the ADV update, for the advected fields Q0 ..
-// Q0+NQ-1 of the order rho, mx, my, mz, E, e, h2: each thread marches along z
+// Q0+NQ-1 of the order rho, mx, my, mz, E, e, h2, hp: each thread marches along z
 // over a segment of cells with a sliding 6-cell window of those fields, so
 // the flux at the upper z face of cell k is the lower one of cell k+1, and the
 // update reads the x and y fluxes written by the x/y face kernels.  Same
@@ -843,7 +870,7 @@ struct BAdvZUpdate {
         const int stride = g.nxy;
         const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
         const T dtdx = T(step_dt(A.a) / A.a.h);
-        const int fld[7] = { RHO, MX, MY, MZ, EN, EI, H2 };
+        const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
         const T ra = T(A.rk.a), rb = T(A.rk.b);
         int ip = i + 1 == g.nx ? 0 : i + 1;
         int jp = j + 1 == g.ny ? 0 : j + 1;
@@ -950,13 +977,23 @@ struct BTail {
             double bx = 0.5 * ((double)U.f[BX][c] + (double)U.f[BX][nbr<0>(g, c, i, j, k, 1)]);
             double by = 0.5 * ((double)U.f[BY][c] + (double)U.f[BY][nbr<1>(g, c, i, j, k, 1)]);
             double bz = 0.5 * ((double)U.f[BZ][c] + (double)U.f[BZ][nbr<2>(g, c, i, j, k, 1)]);
+            const int ion = A.a.ion;
+            double h2 = (double)U.f[H2][c];
+            double hp = ion ? (double)U.f[HP][c] : 0.0;
             if (A.mode == 1) {
-                double h2 = (double)U.f[H2][c];
+                const double dt = step_dt(A.a);
                 h2 = h2 > rho ? rho : h2;
                 h2 = h2 < 0.0 ? 0.0 : h2;
-                if (A.ch.on) h2 = chem_h2(A.ch, A.a.gamma, rho, e, h2, step_dt(A.a));
+                if (ion) {
+                    hp = hp > rho - h2 ? rho - h2 : hp;
+                    hp = hp < 0.0 ? 0.0 : hp;
+                }
+                if (A.ch.on) {
+                    if (ion) chem_ion(A.ch, rho, e, h2, hp, dt, h2, hp);
+                    else h2 = chem_h2(A.ch, A.a.gamma, rho, e, h2, dt);
+                }
                 if (A.ch.cool) {
-                    double en = cooled_e(A.ch, A.a.gamma, rho, e, h2, step_dt(A.a));
+                    double en = ion ? cooled_e_ion(A.ch, rho, e, h2, hp, dt) : cooled_e(A.ch, A.a.gamma, rho, e, h2, dt);
                     E += en - e;
                     e = en;
                     U.f[EN][c] = (T)E;
@@ -965,15 +1002,20 @@ struct BTail {
                 double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
                 double M = 0.5 * (bx * bx + by * by + bz * bz);
                 double ei = E - K - M;
-                if (ei >= 1e-3 * E && (A.a.gamma - 1.0) * ei > M) e = ei;
+                if (ei >= 1e-3 * E && (gamma_cell(ion, A.a.gamma, rho, h2, hp) - 1.0) * ei > M) e = ei;
                 U.f[H2][c] = (T)h2;
                 U.f[EI][c] = (T)e;
                 e = (double)(T)e;
+                h2 = (double)(T)h2;
+                if (ion) {
+                    U.f[HP][c] = (T)hp;
+                    hp = (double)(T)hp;
+                }
             }
             bool ok = rho > 0.0 && e > 0.0 && isfinite(rho) && isfinite(e) && isfinite(E) && isfinite(mx) &&
                       isfinite(my) && isfinite(mz) && isfinite(bx) && isfinite(by) && isfinite(bz);
             if (!ok) atomicOr(A.flags, 1u);
-            spd = ok ? cell_speed(A.a.gamma, rho, mx, my, mz, e, bx, by, bz) : 0.0;
+            spd = ok ? cell_speed(gamma_cell(ion, A.a.gamma, rho, h2, hp), rho, mx, my, mz, e, bx, by, bz) : 0.0;
         }
         block_max_store(spd, A.part, blk);
     }
@@ -1006,7 +1048,7 @@ struct BReduceDt {
     }
 };
 
-// FP64 totals: per-block fixed-order sums of the 10 fields
+// FP64 totals: per-block fixed-order sums of the NF fields
 template <typename T>
 struct BTotalsPartial {
     static constexpr int NT = NTH;
@@ -1065,7 +1107,7 @@ struct BTotalsFinal {
 
 // ---------------------------------------------------------------- state conversion
 
-// primitive (host order rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2) -> conserved
+// primitive (host order rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2, x_hp) -> conserved
 template <typename T>
 struct BInit {
     static constexpr int NT = NTH;
@@ -1075,6 +1117,7 @@ struct BInit {
         const double* Wp;
         Fields<T> U;
         double gamma;
+        int ion;
     };
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -1092,7 +1135,8 @@ struct BInit {
         double bx = 0.5 * (bxf + Wp[5 * N + nbr<0>(g, c, i, j, k, 1)]);
         double by = 0.5 * (byf + Wp[6 * N + nbr<1>(g, c, i, j, k, 1)]);
         double bz = 0.5 * (bzf + Wp[7 * N + nbr<2>(g, c, i, j, k, 1)]);
-        double e = p / (A.gamma - 1.0);
+        double h2 = Wp[8 * N + c] * rho, hp = Wp[9 * N + c] * rho;
+        double e = p / (gamma_cell(A.ion, A.gamma, rho, h2, hp) - 1.0);
         A.U.f[RHO][c] = (T)rho;
         A.U.f[MX][c] = (T)(rho * vx);
         A.U.f[MY][c] = (T)(rho * vy);
@@ -1102,7 +1146,8 @@ struct BInit {
         A.U.f[BX][c] = (T)bxf;
         A.U.f[BY][c] = (T)byf;
         A.U.f[BZ][c] = (T)bzf;
-        A.U.f[H2][c] = (T)(Wp[8 * N + c] * rho);
+        A.U.f[H2][c] = (T)h2;
+        A.U.f[HP][c] = (T)hp;
     }
 };
 

@@ -11,9 +11,9 @@
 namespace mhd {
 
 constexpr int NTH = 256;           // threads per block for cell-parallel kernels
-constexpr int NF = 10;             // conserved fields
+constexpr int NF = 11;             // conserved fields (the last, H+, used by the ionisation network)
 constexpr int NFACE = 7;           // per-face outputs
-enum { RHO = 0, MX, MY, MZ, EN, EI, BX, BY, BZ, H2 };
+enum { RHO = 0, MX, MY, MZ, EN, EI, BX, BY, BZ, H2, HP };
 
 // ---------------------------------------------------------------- geometry
 
@@ -248,19 +248,24 @@ __device__ __forceinline__ void side_right(const Par<T>& P, Side<T>& S, int v)
 // NONADV face state (Sec. 2.4) of one face and the fluxes and edge-field
 // contributions it produces.  Inputs: cell-centre rho, p, Bt1, Bt2 of the left
 // and right cells, the face normal field bn, the two sides' parabolas of
-// (vn, vt1, vt2, Bt1, Bt2, p).  Outputs (7): momentum flux (normal, t1, t2),
+// (vn, vt1, vt2, Bt1, Bt2, p), the adiabatic index gm, or with ion the two
+// cells' gamma_eff.  Outputs (7): momentum flux (normal, t1, t2),
 // energy flux, face normal velocity, E along t1 (B_t2 U_n - B_n U_t2), E along
 // t2 (B_n U_t1 - B_t1 U_n).
 template <typename T>
 __device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr, T b1r, T b2r, T bn,
-                                           const Side<T>& L, const Side<T>& R, T gm, T ydx, T out[7])
+                                           const Side<T>& L, const Side<T>& R, T gm, T gml, T gmr, bool ion, T ydx,
+                                           T out[7])
 {
     const T eps = Eps<T>::v;
-    // face averages (sqrt(rho) weights; cross weights for Bt)
+    // face averages (sqrt(rho) weights; cross weights for Bt); with the
+    // ionisation network the adiabatic index is the cells' gamma_eff averaged
+    // with the weights of p
     T sl = root_nr(rl), sr = root_nr(rr);
     T iw = rcp_nr(sl + sr);
     T rho = (sl * rl + sr * rr) * iw;
     T p = (sl * pl + sr * pr) * iw;
+    if (ion) gm = (sl * gml + sr * gmr) * iw;
     T bt1 = (sl * b1r + sr * b1l) * iw;
     T bt2 = (sl * b2r + sr * b2l) * iw;
 
@@ -363,8 +368,49 @@ __device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr,
 struct ChemArgs {
     int on;     // chemistry stage
     int cool;   // heating/cooling stage
+    int ion;    // ionisation network (reactions 5-8, H+ field, gamma_eff)
     double n_unit, T_unit, t_unit;
 };
+
+// Sec. 4.3: effective adiabatic index (5 n_H + 5 n_e + 7 n_H2) / (3 n_H +
+// 3 n_e + 5 n_H2) of a cell with the ionisation network (n_e = n_H+), the
+// constant gamma without it
+__device__ __forceinline__ double gamma_cell(int ion, double gamma, double rho, double h2, double hp)
+{
+    if (!ion) return gamma;
+    double nH = rho - h2 - hp, nH2 = 0.5 * h2, ne = hp;
+    return (5.0 * nH + 5.0 * ne + 7.0 * nH2) / (3.0 * nH + 3.0 * ne + 5.0 * nH2);
+}
+
+// rates of reactions 5-8 (appendix): cosmic-ray ionisation per H atom (s^-1),
+// collisional ionisation (a polynomial in ln of T in eV), radiative and grain
+// recombination (cm^3 s^-1, log = log10)
+__device__ __forceinline__ double rate_k6(double T)
+{
+    const double l = log(T * 8.617333262e-5);
+    const double c[9] = { -32.7, 13.5, -5.7, 1.5, -0.3, 3.4e-2, -2.6e-3, 1.1e-4, -2.1e-6 };
+    double s = 0.0, lp = 1.0;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        s += c[i] * lp;
+        lp *= l;
+    }
+    return exp(s);
+}
+
+__device__ __forceinline__ double rate_k7(double T)
+{
+    double x = log10(T);
+    double num = -10.78 + 4.68 * x - 0.87 * x * x + 0.08 * x * x * x - 3.87e-3 * x * x * x * x;
+    double den = 1.0 - 0.38 * x + 0.06 * x * x - 5.1e-3 * x * x * x + 2.4e-4 * x * x * x * x;
+    return pow(10.0, num / den);
+}
+
+__device__ __forceinline__ double rate_k8(double T)
+{
+    double inner = 1.0 + 5.087e2 * pow(T, 1.586e-2) * pow(10.0, -1.8892 - 4.4e-5 * log10(T));
+    return 12.25e-14 / (1.0 + 8.074e-6 * pow(10.0, 2.756) * inner);
+}
 
 // Sec. 2.7 with the appendix rates of reactions 1-4 (optically thin k4)
 __device__ double chem_h2(const ChemArgs& ch, double gamma, double rho, double e, double h2, double dt)
@@ -442,6 +488,95 @@ __device__ double cooled_e(const ChemArgs& ch, double gamma, double rho, double 
     double de = dt * ch.t_unit * heat_cool(ch, gamma, rho, e, h2) / eu;
     double mu = 1.0 / (1.0 - 0.5 * (h2 / rho));
     double efloor = rho * t_floor / (ch.T_unit * mu * (gamma - 1.0));
+    double lo = e < efloor ? e : efloor;
+    double en = e + de;
+    return en < lo ? lo : en;
+}
+
+// Sec. 2.7 with reactions 1-8 (ionisation network): semi-implicit updates of
+// n_H2 and n_H+ = n_e from the state at the start of the step, n_H = n_u (rho
+// - h2 - hp); H2 clamped to [0, n_u (rho - hp) / 2], then H+ to [0, n_u (rho -
+// h2')]; temperature from gamma_eff and the mean mass 1 / (1 - x_H2/2 + x_H+)
+__device__ void chem_ion(const ChemArgs& ch, double rho, double e, double h2, double hp, double dt, double& h2_out,
+                         double& hp_out)
+{
+    double gam = gamma_cell(1, 0.0, rho, h2, hp);
+    double p = (gam - 1.0) * e;
+    double mu = 1.0 / (1.0 - 0.5 * (h2 / rho) + hp / rho);
+    double T = ch.T_unit * mu * p / rho;
+    double nH = ch.n_unit * (rho - h2 - hp);
+    double nH2 = ch.n_unit * h2 / 2.0;
+    double ne = ch.n_unit * hp;
+    double n = nH + nH2 + ne;
+    double ts = dt * ch.t_unit;
+    double t2 = T / 100.0;
+    double st2 = sqrt(t2);
+    double k1b = 3e-17 * st2 / (1.0 + 0.4 * st2 + 0.2 * t2 + 0.08 * t2 * t2);
+    double k2 = (T > 7390.0) ? 6.11e-14 * exp(-2.93e4 / T) : 2.67e-15 * exp(-(6750.0 / T) * (6750.0 / T));
+    double k3 = (T > 7291.0) ? 5.22e-14 * exp(-3.22e4 / T)
+                             : 3.17e-15 * exp(-(4060.0 / T) - (7500.0 / T) * (7500.0 / T));
+    double k4 = 3.3 * 1.7e-11;
+    double C = k1b * n * nH;
+    double Dd = k2 * nH + k3 * nH2 + k4;
+    double m2 = nH2 + ts * (C - Dd * nH2) / (1.0 + ts * Dd);
+    double m2max = ch.n_unit * (rho - hp) / 2.0;
+    m2 = m2 > m2max ? m2max : m2;
+    m2 = m2 < 0.0 ? 0.0 : m2;
+    double Ci = 6e-18 * nH + rate_k6(T) * nH * ne;
+    double Di = (rate_k7(T) + rate_k8(T)) * ne;
+    double mi = ne + ts * (Ci - Di * ne) / (1.0 + ts * Di);
+    double h2n = 2.0 * m2 / ch.n_unit;
+    double mimax = ch.n_unit * (rho - h2n);
+    mi = mi > mimax ? mimax : mi;
+    mi = mi < 0.0 ? 0.0 : mi;
+    h2_out = h2n;
+    hp_out = mi / ch.n_unit;
+}
+
+// heating/cooling with the ionisation network: the terms of reactions 1-4
+// with gamma_eff, the ion mean mass and n = n_H + n_H2 + n_H+, plus cosmic-ray
+// heating 1.92e-28 n and collisional-ionisation cooling 2.18e-11 erg k6 n_H n_e
+__device__ double heat_cool_ion(const ChemArgs& ch, double rho, double e, double h2, double hp)
+{
+    const double kb_ev = 8.617333262e-5;
+    double gam = gamma_cell(1, 0.0, rho, h2, hp);
+    double p = (gam - 1.0) * e;
+    double mu = 1.0 / (1.0 - 0.5 * (h2 / rho) + hp / rho);
+    double T = ch.T_unit * mu * p / rho;
+    double nH = ch.n_unit * (rho - h2 - hp);
+    double nH2 = ch.n_unit * h2 / 2.0;
+    double ne = ch.n_unit * hp;
+    double n = nH + nH2 + ne;
+    double x = log10(T / 1e4);
+    double t2 = T / 100.0;
+    double st2 = sqrt(t2);
+    double k1b = 3e-17 * st2 / (1.0 + 0.4 * st2 + 0.2 * t2 + 0.08 * t2 * t2);
+    double ncr = pow(10.0, 4.0 - 0.416 * x - 0.327 * x * x);
+    double g1 = 7.2e-12 * (k1b * n * nH) / (1.0 + ncr / n);
+    double g4 = 6.4e-13 * (3.3 * 1.7e-11) * nH2;
+    double lh2 = (T > 1087.0) ? 3.9e-19 * exp(-6118.0 / T) : pow(10.0, -19.24 + 0.474 * x - 1.247 * x * x);
+    double fl2 = (T > 4031.0) ? 1.38e-22 * exp(-9243.0 / T) : pow(10.0, -22.9 - 0.553 * x - 1.148 * x * x);
+    double ll2 = (pow(nH2, 0.77) + 1.2 * pow(nH, 0.77)) * fl2;
+    double l2 = nH2 * lh2 / (1.0 + lh2 / ll2);
+    double a = 1.0 + 1.0 / (kb_ev * T);
+    const double a45 = 1.0 + 1.0 / (kb_ev * 4500.0);
+    double lnf = 0.5 * log(T) + log(a) - a;
+    double lnf45 = 0.5 * log(4500.0) + log(a45) - a45;
+    double ln_ll3 = log(8.18e-13) + log(n) + log(6.29e-15 * 1.38) + lnf - lnf45;
+    double ln_lh3 = log(1.1e-13) - 6744.0 / T;
+    double l3 = nH2 * exp(ln_lh3) / (1.0 + exp(ln_lh3 - ln_ll3));
+    double g5 = 1.92e-28 * n;
+    double l6 = 2.18e-11 * rate_k6(T) * nH * ne;
+    return (g1 + g4 + g5) - (l2 + l3 + l6);
+}
+
+__device__ double cooled_e_ion(const ChemArgs& ch, double rho, double e, double h2, double hp, double dt)
+{
+    const double kb = 1.380649e-16, t_floor = 10.0;
+    double eu = ch.n_unit * kb * ch.T_unit;
+    double de = dt * ch.t_unit * heat_cool_ion(ch, rho, e, h2, hp) / eu;
+    double mu = 1.0 / (1.0 - 0.5 * (h2 / rho) + hp / rho);
+    double efloor = rho * t_floor / (ch.T_unit * mu * (gamma_cell(1, 0.0, rho, h2, hp) - 1.0));
     double lo = e < efloor ? e : efloor;
     double en = e + de;
     return en < lo ? lo : en;

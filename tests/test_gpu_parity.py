@@ -47,7 +47,7 @@ def field_scale(U, f):
 
 def assert_fields_close(G, U, tol, what=""):
     worst = []
-    for f in range(10):
+    for f in range(binding.NFIELDS):
         e = float(np.abs(G[f] - U[f]).sum()) / max(field_scale(U, f), 1e-300)
         worst.append(e)
         assert e <= tol, "%s field %s: L1 rel %.3e (max abs %.3e)" % (what, binding.FIELDS[f], e,
@@ -87,7 +87,7 @@ def test_c1_ten_steps_fp64():
     G = box.get_state()
     assert_fields_close(G, U, TOL64, "c1")
     tg, to = box.totals(), oracle.totals(P, U)
-    absq = np.abs(U).reshape(10, -1).sum(axis=1)
+    absq = np.abs(U).reshape(binding.NFIELDS, -1).sum(axis=1)
     assert np.all(np.abs(tg - to) <= TOL64 * absq)
     # conservation on the GPU: mass (= total hydrogen), momentum, energy, face flux
     for f in (0, 1, 2, 3, 4, 6, 7, 8):
@@ -133,7 +133,7 @@ def test_substage_right_hand_sides(theta):
         box.set_state(U)
         box.debug_stage(stage, dt)
         G = box.get_state()
-        for f in range(10):
+        for f in range(binding.NFIELDS):
             scale = max(np.abs(ref[f]).sum(), 1e-300)
             assert np.abs(G[f] - ref[f]).sum() <= TOL64 * scale + 1e-300, (stage, binding.FIELDS[f])
 
@@ -277,10 +277,10 @@ def test_fp32_mixed_against_fp64(recipe):
         b.step(dt)
     A, B = a.get_state(), b.get_state()
     ta, tb = a.totals(), b.totals()
-    absq = np.abs(A).reshape(10, -1).sum(axis=1)
+    absq = np.abs(A).reshape(binding.NFIELDS, -1).sum(axis=1)
     for f in (0, 1, 2, 3, 4, 6, 7, 8):
         assert abs(ta[f] - tb[f]) <= 1e-5 * absq[f], (binding.FIELDS[f], abs(ta[f] - tb[f]) / absq[f])
-    errs = [rel_l1(B[f], A[f]) for f in range(10)]
+    errs = [rel_l1(B[f], A[f]) for f in range(binding.NFIELDS)]
     print("fp32 field L1 rel", ["%.1e" % e for e in errs], flush=True)
     assert max(errs[:9]) < 1e-3
 
