@@ -136,22 +136,22 @@ def _roofline(timing, ncell, esz, workload):
     return out
 
 
-def _cpu_baseline(n=192, steps=3, cooling=False, grav_G=0.0):
+def _cpu_baseline(n=192, steps=3, cooling=False, grav_G=0.0, ionisation=False):
     import oracle
     from paper_1608_08748_amd import inputs
     oracle.build(force=False)
     if grav_G > 0:
         n, steps = 64, 2      # the oracle's Poisson solve is a plain O(n^4) transform
     W = inputs.c2(n=n)
-    P = oracle.make_params(W.shape[1:], cooling=cooling, grav_G=grav_G)
+    P = oracle.make_params(W.shape[1:], cooling=cooling, grav_G=grav_G, ionisation=ionisation)
     U = oracle.prim_to_cons(P, W)
     t0 = time.perf_counter()
     oracle.run(P, U, steps)
     el = time.perf_counter() - t0
     return {"value": round(n ** 3 * steps / el, 1), "unit": "cell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": "c2 recipe (rms Mach 5, beta 1, seed 2)%s%s at %d^3, %d steps, %.1f s"
+            "kind": "oracle", "sample": "c2 recipe (rms Mach 5, beta 1, seed 2)%s%s%s at %d^3, %d steps, %.1f s"
             % (" with heating/cooling" if cooling else "", " with self-gravity" if grav_G > 0 else "",
-               n, steps, el)}
+               " with the ionisation network" if ionisation else "", n, steps, el)}
 
 
 def _serving_bench(args):
@@ -290,6 +290,8 @@ def main():
                     help="c1-c3: add the heating/cooling stage (Sec. 2 stage 5) after chemistry")
     ap.add_argument("--gravity", action="store_true",
                     help="c1-c3: add self-gravity (FFT Poisson solve each step, sources in NONADV)")
+    ap.add_argument("--ionisation", action="store_true",
+                    help="c1-c3: add the ionisation network (reactions 5-8, H+ field, gamma_eff)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -320,7 +322,10 @@ def main():
     gG = binding.gravity_G() if args.gravity else 0.0
     if gG > 0:
         cfg["desc"] += " + self-gravity (G = %.4f code units)" % gG
-    box = binding.Box(shape, precision=cfg["precision"], cooling=cool, grav_G=gG)
+    ion = bool(args.ionisation)
+    if ion:
+        cfg["desc"] += " + ionisation network (H+ from zero)"
+    box = binding.Box(shape, precision=cfg["precision"], cooling=cool, grav_G=gG, ionisation=ion)
     box.init_state(W)
     for _ in range(args.warmup):
         box.step(box.cfl_dt())
@@ -332,7 +337,7 @@ def main():
         # the FP64 run of the same seed first; the FP32 run replays its dt sequence
         del box
         torch.cuda.empty_cache()
-        ref = binding.Box(shape, precision=binding.FP64, cooling=cool, grav_G=gG)
+        ref = binding.Box(shape, precision=binding.FP64, cooling=cool, grav_G=gG, ionisation=ion)
         ref.init_state(W)
         el64, ref_dts = _timed_run(ref, steps)
         t64 = ref.totals()
@@ -342,7 +347,7 @@ def main():
         extra["fp64_same_seed"] = {"value": round(ncell * steps / el64, 1), "ms_per_step": round(el64 / steps * 1e3, 3)}
         del ref
         torch.cuda.empty_cache()
-        box = binding.Box(shape, precision=cfg["precision"], cooling=cool, grav_G=gG)
+        box = binding.Box(shape, precision=cfg["precision"], cooling=cool, grav_G=gG, ionisation=ion)
         box.init_state(W)
 
     _copy_calibration()
@@ -357,7 +362,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": cfg["dtype"],
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "cells": ncell, "grid": list(shape)[::-1], "cfl": 0.3,
-                   "gamma": 5.0 / 3.0, "theta": 1.0, "heating_cooling": cool, "self_gravity": gG > 0,
+                   "gamma": 5.0 / 3.0, "theta": 1.0, "heating_cooling": cool, "self_gravity": gG > 0, "ionisation": ion,
                    "parallelism": "single GPU"},
         "roofline": _roofline(timing, ncell, esz, args.config),
         "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
@@ -371,7 +376,7 @@ def main():
         out.update(extra)
         del G32
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(cooling=cool, grav_G=gG)
+        out["cpu_baseline"] = _cpu_baseline(cooling=cool, grav_G=gG, ionisation=ion)
     print(json.dumps(out), flush=True)
 
 
