@@ -465,16 +465,17 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
     e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
 }
 
-template <typename T, int D, class Emit>
+template <typename T, int D, int NQ, class Emit>
 void emit_adv_face(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a)
 {
-    typename BAdvFace<T, D>::Args fa;
+    typename BAdvFace<T, D, NQ>::Args fa;
     fa.g = b->g;
     fa.U = cview(in);
     fa.a = a;
     fa.F = reinterpret_cast<T*>(b->F[D]);
-    e.template launch<BAdvFace<T, D>>(MHD_K_ADV_FACE, b->nblocks, 0, fa);
+    e.template launch<BAdvFace<T, D, NQ>>(MHD_K_ADV_FACE, b->nblocks, 0, fa);
 }
+
 
 template <typename T, class Emit>
 void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg)
@@ -482,8 +483,15 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
-    emit_adv_face<T, 0>(b, e, in, a);
-    emit_adv_face<T, 1>(b, e, in, a);
+    // one face per thread: an LDS row scheme that computes each cell's
+    // slopes once measured slower here (block barriers, fewer waves)
+    if (b->p.ionisation) {
+        emit_adv_face<T, 0, 8>(b, e, in, a);
+        emit_adv_face<T, 1, 8>(b, e, in, a);
+    } else {
+        emit_adv_face<T, 0, 7>(b, e, in, a);
+        emit_adv_face<T, 1, 7>(b, e, in, a);
+    }
     // z faces marched together with the update of every cell
     AdvZArgs<T> ua;
     ua.g = b->g;

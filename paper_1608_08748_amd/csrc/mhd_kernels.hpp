@@ -766,10 +766,10 @@ struct BFftYZ {
 
 // ---------------------------------------------------------------- ADV
 
-// ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, 7 x N
-// (8 x N with the ionisation network), in the order rho, mx, my, mz, E, e, h2,
-// hp.
-template <typename T, int D>
+// ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, NQ x
+// N (NQ = 7, or 8 with the ionisation network), in the order rho, mx, my, mz,
+// E, e, h2, hp.
+template <typename T, int D, int NQ>
 struct BAdvFace {
     static constexpr int NT = NTH;
     static constexpr bool XCD = D == 1;   // the y stencil reads rows of neighbouring blocks
@@ -797,12 +797,9 @@ struct BAdvFace {
         T vf = (A.U.f[MX + D][idx[2]] * rsl + A.U.f[MX + D][c] * rsr) * rcp_nr(rl * rsl + rr * rsr);
         bool upw = vf >= T(0);
         T y = upw ? ydx * vf : ydx * (-vf);
-        // the ionisation network advects H+ as an eighth field
-        const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
-        const int nq = A.a.ion ? 8 : 7;
+                const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            if (q >= nq) break;
+        for (int q = 0; q < NQ; q++) {
             const T* u = A.U.f[fld[q]];
             int o = upw ? 0 : 1;
             T q0 = u[idx[o]], q1 = u[idx[o + 1]], q2 = u[idx[o + 2]], q3 = u[idx[o + 3]], q4 = u[idx[o + 4]];
