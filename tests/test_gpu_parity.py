@@ -286,15 +286,21 @@ def test_fp32_mixed_against_fp64(recipe):
 
 
 @pytest.mark.slow
-def test_c2_full_size_one_step():
-    # configuration 2 at its full size (256^3, FP64), first step against the oracle
+def test_c2_full_size_first_steps():
+    # configuration 2 at its full size (256^3, FP64) and in the launch
+    # configuration the benchmark times: the first five steps against the
+    # oracle, fields (L1) and conserved totals
     n = int(os.environ.get("MHD_FULL_N", "256"))
     W = inputs.c2(n=n)
     box, P, U = _pair(W)
-    dt = oracle.cfl_dt(P, U)
-    assert abs(box.cfl_dt() - dt) <= 1e-13 * dt
-    box.step(dt)
-    t = time.time()
-    oracle.step(P, U, dt)
-    print("oracle 256^3 step: %.1f s" % (time.time() - t), flush=True)
-    assert_fields_close(box.get_state(), U, TOL64, "c2 full")
+    for s in range(5):
+        dt = oracle.cfl_dt(P, U)
+        assert abs(box.cfl_dt() - dt) <= 1e-13 * dt, s
+        box.step(dt)
+        t = time.time()
+        oracle.step(P, U, dt)
+        print("c2 step %d: oracle %.1f s" % (s, time.time() - t), flush=True)
+    assert_fields_close(box.get_state(), U, TOL64, "c2 full, 5 steps")
+    tg, to = box.totals(), oracle.totals(P, U)
+    absq = np.abs(U).reshape(binding.NFIELDS, -1).sum(axis=1)
+    assert np.all(np.abs(tg - to) <= TOL64 * absq), (tg - to) / np.maximum(absq, 1e-300)
