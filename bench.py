@@ -102,7 +102,7 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 # write 1 GiB
 TRAFFIC = {
     # average of the x-row, y-march and z-march face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("25489c8f72b1aa95", 2105763840),
+    ("c2", 8, "nonadv_face"): ("e464a7d7fe22b806", 2105771349),
 }
 
 
