@@ -81,3 +81,49 @@ def test_gravity_parameters_validated():
 def test_gravity_constant_in_code_units():
     # G n_u m_H t_u^2 with n_u = 5 cm^-3, t_u = 256 pc / sqrt(k_B 5000 K / m_H)
     assert abs(binding.gravity_G() - 0.84486) < 1e-4
+
+
+def _host_bound_box(**kw):
+    """A box bound to a host buffer standing in for the workspace: mhd_create
+    only records the pointer, and the calls below return before any device
+    work."""
+    p = binding.make_params((8, 8, 8), **kw)
+    need = binding.workspace_bytes(p)
+    buf = ctypes.create_string_buffer(need + 256)
+    addr = (ctypes.addressof(buf) + 255) & ~255
+    p.workspace, p.workspace_bytes = addr, need
+    h = ctypes.c_void_p()
+    assert binding.lib().mhd_create(ctypes.byref(p), ctypes.byref(h)) == binding.MHD_OK
+    return h, buf
+
+
+def test_host_side_argument_checks():
+    L = binding.lib()
+    h, buf = _host_bound_box()
+    phi = (ctypes.c_double * 512)()
+    # no self-gravity on this box
+    assert L.mhd_get_potential(h, phi) == binding.MHD_EINVAL
+    # unknown stage selector
+    assert L.mhd_debug_stage(h, 99, 1e-3) == binding.MHD_EINVAL
+    # a step must be finite and positive
+    for dt in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.mhd_step(h, dt) == binding.MHD_EINVAL, dt
+    # unaligned workspace
+    p = binding.make_params((8, 8, 8))
+    p.workspace, p.workspace_bytes = ctypes.addressof(buf) | 8, binding.workspace_bytes(p)
+    h2 = ctypes.c_void_p()
+    assert L.mhd_create(ctypes.byref(p), ctypes.byref(h2)) == binding.MHD_EINVAL
+    assert L.mhd_destroy(h) == binding.MHD_OK
+
+
+def test_ionisation_parameters_validated():
+    base = binding.workspace_bytes(binding.make_params((8, 8, 8)))
+    ion = binding.workspace_bytes(binding.make_params((8, 8, 8), ionisation=True))
+    # one more primitive (gamma_eff) and one more ADV flux per direction
+    assert ion > base
+    p = binding.make_params((8, 8, 8), ionisation=True)
+    p.ionisation = 2
+    assert binding.workspace_bytes(p) == 0
+    p = binding.make_params((8, 8, 8), ionisation=True, units=(0.0, 5000.0, 1e15))
+    assert binding.workspace_bytes(p) == 0
+    assert binding.NFIELDS == 11 and binding.NPRIM == 10
