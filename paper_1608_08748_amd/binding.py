@@ -107,8 +107,8 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libmhdchem.so is not built (run __graft_entry__.build() or "
-                          "python -m paper_1608_08748_amd.build); there is no fallback path")
+        raise ImportError("libmhdchem.so is not built (run python -m paper_1608_08748_amd.build); "
+                          "there is no fallback path")
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(MhdParams)
     B = ctypes.c_void_p
