@@ -35,8 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # stored values (x 8 B for FP64, x 4 B for FP32): the fields the kernel must
 # read once and write once, with neighbour re-reads excluded
 ALG_VALUES = {
-    "prim": 8 + 8,            # rho, m(3), e, b(3) -> rho, v(3), Bc(3), p
-    "nonadv_face": 8 + 7,     # 7 primitives + face B_n -> 7 face outputs
+    "nonadv_face": 8 + 7,     # rho, m(3), e, 2 transverse b, face b_n -> 7 face outputs
     "nonadv_update": 21 + 8 + 8 + 8,   # 3 x 7 face outputs, U and Q0 (8 fields each) -> 8 fields
     "adv_face": 7 + 7,        # 7 advected fields -> 7 fluxes
     "adv_update": 21 + 7 + 7 + 7,      # 3 x 7 fluxes, U, Q0 -> 7 fields

@@ -176,7 +176,9 @@ int mhd_debug_stage(mhd_box *b, int stage, double dt);
 
 /* Kernel classes timed by mhd_set_timing / mhd_get_timing. */
 enum {
-    MHD_K_PRIM = 0,          /* NONADV primitive pass                 */
+    MHD_K_SETUP = 0,         /* state set-up (init_state, set_state); the step has no
+                              * primitive pass: the NONADV face kernels form the
+                              * primitives they read from the conserved state */
     MHD_K_NONADV_FACE = 1,   /* NONADV face Riemann solve (per axis)  */
     MHD_K_NONADV_UPDATE = 2, /* NONADV flux/CT update + RK            */
     MHD_K_ADV_FACE = 3,      /* ADV face fluxes (per axis)            */

@@ -20,7 +20,7 @@ STAGE_NONADV, STAGE_ADV, STAGE_TAIL, STAGE_NONADV_RHS, STAGE_ADV_RHS = 1, 2, 3, 
 FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2", "hp")
 NFIELDS = len(FIELDS)      # conserved fields (hp = rho_H+, zero without the ionisation network)
 NPRIM = 10                 # primitive fields: rho, vx, vy, vz, p, bx_f, by_f, bz_f, x_h2, x_hp
-KCLASSES = ("prim", "nonadv_face", "nonadv_update", "adv_face", "adv_update", "tail", "reduce", "poisson")
+KCLASSES = ("setup", "nonadv_face", "nonadv_update", "adv_face", "adv_update", "tail", "reduce", "poisson")
 NKCLASS = len(KCLASSES)
 
 # chemistry unit map: 5 H nuclei per cm^3 per unit density, T_u = 5000 K,

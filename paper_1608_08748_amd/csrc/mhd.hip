@@ -46,7 +46,6 @@ struct mhd_box {
     size_t esz;        // bytes per stored value
     int nblocks;       // cell-parallel blocks of NTH threads
     char* slot[3];     // three Runge-Kutta copies of the NF fields
-    char* W;           // primitives, 8 x N (9 x N with gamma_eff)
     char* F[3];        // per-direction face outputs, 7 x N each (8 x N with the ionisation network)
     double* part;      // per-block partials: NF x nblocks
     uint32_t* flags;
@@ -80,7 +79,7 @@ int group_of(int f)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t slot, W, F, part, misc, grav, total;
+    size_t slot, F, part, misc, grav, total;
 };
 
 bool pow2_upto(int n, int cap) { return n >= 1 && n <= cap && (n & (n - 1)) == 0; }
@@ -133,7 +132,6 @@ Layout layout_of(const int32_t n[3], int precision, bool grav, bool ion)
     size_t esz = precision == MHD_FP64 ? 8 : 4;
     size_t nb = (N + NTH - 1) / NTH;
     L.slot = align256(NF * N * esz);
-    L.W = align256((ion ? 9 : 8) * N * esz);   // + gamma_eff with the ionisation network
     size_t fbytes = align256(face_values(ion) * N * esz);
     // the face scratch doubles as host staging (MHD_NPRIM or NF FP64 fields)
     size_t stage = align256((size_t)NF * N * 8);
@@ -147,7 +145,7 @@ Layout layout_of(const int32_t n[3], int precision, bool grav, bool ion)
         L.grav = align256(N * esz);
         for (int d = 0; d < 3; d++) L.grav += align256((size_t)n[d] * 2 * esz) + align256(n[d] * 8);
     }
-    L.total = 3 * L.slot + L.W + L.F + L.part + L.misc + L.grav;
+    L.total = 3 * L.slot + L.F + L.part + L.misc + L.grav;
     return L;
 }
 
@@ -168,8 +166,6 @@ void box_bind(mhd_box* b, const mhd_params* p, const Layout& L)
         b->slot[s] = w;
         w += L.slot;
     }
-    b->W = w;
-    w += L.W;
     size_t fbytes = align256(face_values(p->ionisation != 0) * (size_t)b->g.n * b->esz);
     for (int d = 0; d < 3; d++) b->F[d] = w + d * fbytes;
     w += L.F;
@@ -360,8 +356,8 @@ struct MultiEmit {
 
 // ---------------------------------------------------------------- the step program
 
-template <typename T, class Emit>
-void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, const StepArgs& a)
+template <typename T, bool ION, class Emit>
+void emit_nonadv_faces_t(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a, bool first)
 {
     const Geo& g = b->g;
     T* F0 = reinterpret_cast<T*>(b->F[0]);
@@ -369,10 +365,13 @@ void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, con
     T* F2 = reinterpret_cast<T*>(b->F[2]);
     FaceArgs<T> fa;
     fa.g = g;
-    fa.W = W;
+    fa.U = cview(in);
     fa.a = a;
+    fa.flags = b->flags;
+    // the x-face launch of the first substage checks an explicit dt against
+    // the last device CFL bound
+    fa.dt_cfl = first ? b->dt_dev : nullptr;
     // x faces: whole rows per block when a row fits one block, else one face per thread
-    fa.bface = in.f[BX];
     fa.F = F0;
     const int maxt = sizeof(T) == 8 ? 512 : 1024;
     if (g.nx <= maxt) {
@@ -382,16 +381,17 @@ void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, con
         fa.seg = 0;
         int blocks = (rows + rpb - 1) / rpb;
         if (g.nx <= 256)
-            e.template launch<BFaceXRows<T, 256>>(MHD_K_NONADV_FACE, blocks, 256 * 18 * sizeof(T), fa);
+            e.template launch<BFaceXRows<T, 256, ION>>(MHD_K_NONADV_FACE, blocks, 256 * 18 * sizeof(T), fa);
         else if (g.nx <= 512)
-            e.template launch<BFaceXRows<T, 512>>(MHD_K_NONADV_FACE, blocks, 512 * 18 * sizeof(T), fa);
+            e.template launch<BFaceXRows<T, 512, ION>>(MHD_K_NONADV_FACE, blocks, 512 * 18 * sizeof(T), fa);
         else if constexpr (sizeof(T) == 4)   // 1024-thread rows only in FP32 (register budget)
-            e.template launch<BFaceXRows<T, 1024>>(MHD_K_NONADV_FACE, blocks, 1024 * 18 * sizeof(T), fa);
+            e.template launch<BFaceXRows<T, 1024, ION>>(MHD_K_NONADV_FACE, blocks, 1024 * 18 * sizeof(T), fa);
     } else {
         fa.rpb = 0;
         fa.seg = 0;
-        e.template launch<BFacePair<T, 0>>(MHD_K_NONADV_FACE, b->nblocks, 0, fa);
+        e.template launch<BFacePair<T, 0, ION>>(MHD_K_NONADV_FACE, b->nblocks, 0, fa);
     }
+    fa.dt_cfl = nullptr;
     // y and z faces: marching segments
     constexpr int MARCH_SEG = 32;
     for (int D = 1; D <= 2; D++) {
@@ -399,15 +399,25 @@ void emit_nonadv_faces(mhd_box* b, Emit& e, const T* W, const Fields<T>& in, con
         const int no = D == 1 ? g.nz : g.ny;
         fa.seg = nd < MARCH_SEG ? nd : MARCH_SEG;
         fa.rpb = 0;
-        fa.bface = in.f[D == 1 ? BY : BZ];
         fa.F = D == 1 ? F1 : F2;
         long long threads = (long long)g.nx * no * ((nd + fa.seg - 1) / fa.seg);
         int blocks = (int)((threads + NTH - 1) / NTH);
         if (D == 1)
-            e.template launch<BFaceMarch<T, 1>>(MHD_K_NONADV_FACE, blocks, 0, fa);
+            e.template launch<BFaceMarch<T, 1, ION>>(MHD_K_NONADV_FACE, blocks, 0, fa);
         else
-            e.template launch<BFaceMarch<T, 2>>(MHD_K_NONADV_FACE, blocks, 0, fa);
+            e.template launch<BFaceMarch<T, 2, ION>>(MHD_K_NONADV_FACE, blocks, 0, fa);
     }
+}
+
+// NONADV faces of the three directions; the primitives are formed inside the
+// face kernels from the substage input state
+template <typename T, class Emit>
+void emit_nonadv_faces(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a, bool first)
+{
+    if (b->p.ionisation)
+        emit_nonadv_faces_t<T, true>(b, e, in, a, first);
+    else
+        emit_nonadv_faces_t<T, false>(b, e, in, a, first);
 }
 
 // z cells per thread in the z-marching update kernels
@@ -438,17 +448,8 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
-    T* W = reinterpret_cast<T*>(b->W);
-    typename BPrim<T>::Args pa;
-    pa.g = b->g;
-    pa.U = cview(in);
-    pa.W = W;
-    pa.a = a;
-    pa.flags = b->flags;
-    pa.dt_cfl = first ? b->dt_dev : nullptr;
-    e.template launch<BPrim<T>>(MHD_K_PRIM, b->nblocks, 0, pa);
-    emit_nonadv_faces<T>(b, e, W, in, a);
-    typename BNonadvUpdate<T>::Args ua;
+    emit_nonadv_faces<T>(b, e, in, a, first);
+    NonadvUpdateArgs<T> ua;
     ua.g = b->g;
     ua.U = cview(in);
     ua.S = cview(S);
@@ -461,8 +462,10 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
     ua.dbg = dbg;
     ua.zt = ztile_of(b->g);
     ua.phi = b->grav ? reinterpret_cast<const T*>(b->phi) : nullptr;
-    ua.gam = b->p.ionisation ? W + (size_t)8 * b->g.n : nullptr;
-    e.template launch<BNonadvUpdate<T>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
+    if (b->p.ionisation)
+        e.template launch<BNonadvUpdate<T, true>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
+    else
+        e.template launch<BNonadvUpdate<T, false>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
 }
 
 template <typename T, int D, int NQ, class Emit>
@@ -704,13 +707,13 @@ int load_f64(mhd_box* b, const double* host, bool prim)
         ia.U = u;
         ia.gamma = b->p.gamma;
         ia.ion = b->p.ionisation;
-        e.template launch<BInit<T>>(0, b->nblocks, 0, ia);
+        e.template launch<BInit<T>>(MHD_K_SETUP, b->nblocks, 0, ia);
     } else {
         typename BFromF64<T>::Args ia;
         ia.g = b->g;
         ia.src = stage;
         ia.U = u;
-        e.template launch<BFromF64<T>>(0, b->nblocks, 0, ia);
+        e.template launch<BFromF64<T>>(MHD_K_SETUP, b->nblocks, 0, ia);
     }
     BClearFlags::Args ca;
     ca.flags = b->flags;

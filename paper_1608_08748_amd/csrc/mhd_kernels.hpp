@@ -7,6 +7,8 @@
 
 #include "mhd_math.hpp"
 
+#include <type_traits>
+
 namespace mhd {
 
 struct StepArgs {
@@ -73,14 +75,19 @@ __device__ __forceinline__ bool ztile_cell(const Geo& g, const ZTile& z, int blk
     return ly < z.ty && i < g.nx && j < g.ny && k0 < g.nz;
 }
 
+// occupancy floor: a body may ask for at least MINW waves per SIMD (the
+// compiler then caps its registers); default 1
+template <class Body, class = void> struct MinWaves { static constexpr int v = 1; };
+template <class Body> struct MinWaves<Body, std::void_t<decltype(Body::MINW)>> { static constexpr int v = Body::MINW; };
+
 template <class Body>
-__global__ __launch_bounds__(Body::NT) void k_one(typename Body::Args a)
+__global__ __launch_bounds__(Body::NT) __attribute__((amdgpu_waves_per_eu(MinWaves<Body>::v))) void k_one(typename Body::Args a)
 {
     Body::run(a, logical_block<Body>(), (int)threadIdx.x);
 }
 
 template <class Body>
-__global__ __launch_bounds__(Body::NT) void k_many(const typename Body::Args* __restrict__ tab,
+__global__ __launch_bounds__(Body::NT) __attribute__((amdgpu_waves_per_eu(MinWaves<Body>::v))) void k_many(const typename Body::Args* __restrict__ tab,
                                                    const int* __restrict__ bstart, int nbox)
 {
     int blk = logical_block<Body>();
@@ -94,57 +101,60 @@ __global__ __launch_bounds__(Body::NT) void k_many(const typename Body::Args* __
     Body::run(a, blk - bstart[lo], (int)threadIdx.x);
 }
 
-// ---------------------------------------------------------------- NONADV
+// ---------------------------------------------------------------- NONADV: primitive recovery
 
-// primitive state of every cell: rho, vx, vy, vz, Bcx, Bcy, Bcz, p
-template <typename T>
-struct BPrim {
-    static constexpr int NT = NTH;
-    static constexpr bool XCD = false;
-    struct Args {
-        Geo g;
-        CFields<T> U;
-        T* W;
-        StepArgs a;
-        uint32_t* flags;
-        const double* dt_cfl;   // non-null: check the explicit dt against it
-    };
-    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
-    {
-        const Geo& g = A.g;
-        int c = blk * NT + tid;
-        if (c == 0 && A.dt_cfl && !A.a.dt_dev) {
-            if (A.a.dt_val > *A.dt_cfl * (1.0 + A.a.cfl_tol)) atomicOr(A.flags, 2u);
-        }
-        if (c >= g.n) return;
-        int i, j, k;
-        decompose(g, c, i, j, k);
-        const size_t N = (size_t)g.n;
-        T* W = A.W;
-        T rho = A.U.f[RHO][c];
-        W[0 * N + c] = rho;
-        W[1 * N + c] = A.U.f[MX][c] / rho;
-        W[2 * N + c] = A.U.f[MY][c] / rho;
-        W[3 * N + c] = A.U.f[MZ][c] / rho;
-        W[4 * N + c] = T(0.5) * (A.U.f[BX][c] + A.U.f[BX][nbr<0>(g, c, i, j, k, 1)]);
-        W[5 * N + c] = T(0.5) * (A.U.f[BY][c] + A.U.f[BY][nbr<1>(g, c, i, j, k, 1)]);
-        W[6 * N + c] = T(0.5) * (A.U.f[BZ][c] + A.U.f[BZ][nbr<2>(g, c, i, j, k, 1)]);
-        if (A.a.ion) {
-            double gam = gamma_cell(1, 0.0, (double)rho, (double)A.U.f[H2][c], (double)A.U.f[HP][c]);
-            W[8 * N + c] = T(gam);
-            W[7 * N + c] = T(gam - 1.0) * A.U.f[EI][c];
-        } else {
-            W[7 * N + c] = T(A.a.gamma - 1.0) * A.U.f[EI][c];
-        }
+// Primitive variables (Sec. 2: v = m / rho, p = (gamma - 1) e; the cell-centre
+// field averages the cell's two faces) are formed where the NONADV face
+// kernels read them, from the conserved state, so no primitive array passes
+// through memory.  For faces along D a cell contributes the six parabola
+// variables (vn, vt1, vt2, Bt1, Bt2, p) with (n, t1, t2) cyclic from D, its
+// density and its adiabatic index.
+
+// the conserved values one cell needs: rho, m (normal, t1, t2), e, both faces
+// of the two transverse fields (c1, c2: the upper neighbours along t1 and t2)
+// and, with the ionisation network, the H2 and H+ densities
+template <typename T> struct Raw { T rho, mn, m1, m2, e, b1, b1p, b2, b2p, h2, hp; };
+
+template <typename T, int D, bool ION>
+__device__ __forceinline__ void raw_load(const CFields<T>& U, int c, int c1, int c2, Raw<T>& r)
+{
+    constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    r.rho = U.f[RHO][c];
+    r.mn = U.f[MX + D][c];
+    r.m1 = U.f[MX + T1][c];
+    r.m2 = U.f[MX + T2][c];
+    r.e = U.f[EI][c];
+    r.b1 = U.f[BX + T1][c];
+    r.b1p = U.f[BX + T1][c1];
+    r.b2 = U.f[BX + T2][c];
+    r.b2p = U.f[BX + T2][c2];
+    if (ION) {
+        r.h2 = U.f[H2][c];
+        r.hp = U.f[HP][c];
     }
-};
+}
 
-// primitive-array slots of the six parabola variables for faces along D:
-// (vn, vt1, vt2, Bt1, Bt2, p) in the W layout rho, vx, vy, vz, Bcx, Bcy, Bcz, p
-template <int D> struct Vars {
-    static constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-    static constexpr int f[6] = { 1 + D, 1 + T1, 1 + T2, 4 + T1, 4 + T2, 7 };
-};
+// q[0..5] = (vn, vt1, vt2, Bt1, Bt2, p); gam = the cell's gamma (gamma_eff
+// of Sec. 4.3 with the network, in FP64 as the tail computes it)
+template <typename T, bool ION>
+__device__ __forceinline__ void raw_prim(const Raw<T>& r, double gamma, T q[6], T& gam)
+{
+    q[0] = r.mn / r.rho;
+    q[1] = r.m1 / r.rho;
+    q[2] = r.m2 / r.rho;
+    q[3] = T(0.5) * (r.b1 + r.b1p);
+    q[4] = T(0.5) * (r.b2 + r.b2p);
+    if (ION) {
+        double gc = gamma_cell(1, 0.0, (double)r.rho, (double)r.h2, (double)r.hp);
+        gam = T(gc);
+        q[5] = T(gc - 1.0) * r.e;
+    } else {
+        gam = T(gamma);
+        q[5] = T(gamma - 1.0) * r.e;
+    }
+}
+
+// ---------------------------------------------------------------- NONADV faces
 
 template <typename T>
 __device__ __forceinline__ void store_face(T* __restrict__ F, size_t N, int c, const T out[7])
@@ -156,17 +166,28 @@ __device__ __forceinline__ void store_face(T* __restrict__ F, size_t N, int c, c
 template <typename T>
 struct FaceArgs {
     Geo g;
-    const T* W;
-    const T* bface;
+    CFields<T> U;            // substage input state
     T* F;
     StepArgs a;
-    int rpb;    // x rows per block (row kernel)
-    int seg;    // faces per thread (marching kernel)
+    int rpb;                 // x rows per block (row kernel)
+    int seg;                 // faces per thread (marching kernel)
+    uint32_t* flags;
+    const double* dt_cfl;    // non-null: check the explicit dt against this CFL bound
 };
 
+// an explicit dt above the device CFL bound (with its relative slack) latches
+// flag bit 2 for the next synchronising call; one thread of the box checks
+template <typename T>
+__device__ __forceinline__ void check_dt(const FaceArgs<T>& A, int blk, int tid)
+{
+    if (blk == 0 && tid == 0 && A.dt_cfl && !A.a.dt_dev && A.a.dt_val > *A.dt_cfl * (1.0 + A.a.cfl_tol))
+        atomicOr(A.flags, 2u);
+}
+
 // NONADV faces along D, one face per thread, both adjacent parabolas computed
-// by the thread (general fallback for any box)
-template <typename T, int D>
+// by the thread from the primitives of the six cells of its line (general
+// fallback for any box)
+template <typename T, int D, bool ION>
 struct BFacePair {
     static constexpr int NT = NTH;
     static constexpr bool XCD = false;
@@ -174,43 +195,51 @@ struct BFacePair {
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
+        check_dt(A, blk, tid);
         int c = blk * NT + tid;
         if (c >= g.n) return;
-        using V = Vars<D>;
+        constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
         int i, j, k;
         decompose(g, c, i, j, k);
         const size_t N = (size_t)g.n;
-        const T* W = A.W;
-        int idx[6];
+        // the cells of the line share their transverse coordinates, so their
+        // upper transverse neighbours sit at the same offsets
+        const int o1 = nbr<T1>(g, c, i, j, k, 1) - c, o2 = nbr<T2>(g, c, i, j, k, 1) - c;
+        T q[6][6], rho[6], gam[6];
 #pragma unroll
-        for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
+        for (int m = 0; m < 6; m++) {
+            int cm = nbr<D>(g, c, i, j, k, m - 3);
+            Raw<T> rw;
+            raw_load<T, D, ION>(A.U, cm, cm + o1, cm + o2, rw);
+            T qm[6];
+            raw_prim<T, ION>(rw, A.a.gamma, qm, gam[m]);
+#pragma unroll
+            for (int v = 0; v < 6; v++) q[v][m] = qm[v];
+            rho[m] = rw.rho;
+        }
         Side<T> L, R;
 #pragma unroll
         for (int v = 0; v < 6; v++) {
-            const T* q = W + (size_t)V::f[v] * N;
             Par<T> PL, PR;
-            parabola_pair(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], PL, PR);
+            parabola_pair(q[v][0], q[v][1], q[v][2], q[v][3], q[v][4], q[v][5], PL, PR);
             side_left(PL, L, v);
             side_right(PR, R, v);
         }
         T out[7];
         const T gm = T(A.a.gamma);
-        const bool ion = A.a.ion != 0;
-        face_solve(W[idx[2]], W[7 * N + idx[2]], W[(size_t)V::f[3] * N + idx[2]], W[(size_t)V::f[4] * N + idx[2]],
-                   W[idx[3]], W[7 * N + idx[3]], W[(size_t)V::f[3] * N + idx[3]],
-                   W[(size_t)V::f[4] * N + idx[3]], A.bface[c], L, R, gm, ion ? W[8 * N + idx[2]] : gm,
-                   ion ? W[8 * N + idx[3]] : gm, ion, T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+        face_solve(rho[2], q[5][2], q[3][2], q[4][2], rho[3], q[5][3], q[3][3], q[4][3], A.U.f[BX + D][c], L, R,
+                   gm, gam[2], gam[3], ION, T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
         store_face(A.F, N, c, out);
     }
 };
 
-// NONADV faces along x with whole x rows per block: each thread owns one cell
-// and computes, once each, its limited slopes, the interface values at its
-// lower face and its parabolas (Sec. 2.1); neighbours' slopes, interface
-// values and parabola sides come through LDS (periodic wrap inside the row).
-// Dynamic LDS: 18 x NT values, value k of thread t at k * NT + t, reused by
-// the three exchanges.
-template <typename T, int MAXT>
+// NONADV faces along x with whole x rows per block: each thread owns one cell,
+// forms its primitives and computes, once each, its limited slopes, the
+// interface values at its lower face and its parabolas (Sec. 2.1);
+// neighbours' primitives, slopes, interface values and parabola sides come
+// through LDS (periodic wrap inside the row).  Dynamic LDS: 18 x NT values,
+// value k of thread t at k * NT + t, reused by the four exchanges.
+template <typename T, int MAXT, bool ION>
 struct BFaceXRows {
     static constexpr int NT = MAXT;
     static constexpr bool XCD = false;
@@ -219,51 +248,57 @@ struct BFaceXRows {
     {
         extern __shared__ unsigned char smem_raw[];
         T* sm = reinterpret_cast<T*>(smem_raw);
-        using V = Vars<0>;
         const Geo& g = A.g;
         const size_t N = (size_t)g.n;
         const int nx = g.nx;
-        const T* W = A.W;
+        check_dt(A, blk, tid);
         int r = tid / nx;
         int i = tid - r * nx;
         int row = blk * A.rpb + r;
         bool act = r < A.rpb && row < g.ny * g.nz;
         int rowbase = row * nx;
-        int il = i == 0 ? nx - 1 : i - 1;
-        int tl = r * nx + il;                          // thread of the left cell
-        int tr = r * nx + (i + 1 == nx ? 0 : i + 1);   // thread of the right cell
-        // every global value the thread needs is read before the first
-        // exchange: the 5-cell line of each variable and the two cells'
-        // densities and face normal field (the pressures and transverse
-        // fields of the face solve are line values q1, q2)
-        T q0[6], q1[6], q2[6], q3[6], q4[6], dm[6], fl[6];
-        T rl = T(0), rr = T(0), bn = T(0);
+        const int rb = r * nx;
+        const int tl = rb + (i == 0 ? nx - 1 : i - 1);   // thread of the left cell
+        const int tr = rb + (i + 1 == nx ? 0 : i + 1);   // thread of the right cell
+        const int tm2 = rb + wrapc(i - 2, nx), tp2 = rb + wrapc(i + 2, nx);
         const T gm = T(A.a.gamma);
-        const bool ion = A.a.ion != 0;
-        T gl = gm, gr = gm;
-        const int im2 = wrapc(i - 2, nx), ip1 = wrapc(i + 1, nx), ip2 = wrapc(i + 2, nx);
-        // slopes of the own cell
+
+        // own cell: conserved values (every global load of the thread), primitives
+        T q2[6], rho = T(0), gam = gm, bn = T(0);
+        if (act) {
+            int j = row % g.ny, k = row / g.ny;
+            int c = rowbase + i;
+            int c1 = c + ((j + 1 == g.ny ? 0 : j + 1) - j) * nx;
+            int c2 = c + ((k + 1 == g.nz ? 0 : k + 1) - k) * g.nxy;
+            Raw<T> rw;
+            raw_load<T, 0, ION>(A.U, c, c1, c2, rw);
+            bn = A.U.f[BX][c];
+            raw_prim<T, ION>(rw, A.a.gamma, q2, gam);
+            rho = rw.rho;
+#pragma unroll
+            for (int v = 0; v < 6; v++) sm[v * NT + tid] = q2[v];
+            sm[6 * NT + tid] = rho;
+            if (ION) sm[7 * NT + tid] = gam;
+        }
+        __syncthreads();
+        // the 5-cell line of each variable; the left cell's density (and
+        // gamma); slopes of the own cell
+        T q0[6], q1[6], q3[6], q4[6], dm[6], fl[6];
+        T rl = T(0), gl = gm;
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                const T* qv = W + (size_t)V::f[v] * N + rowbase;
-                q0[v] = qv[im2];
-                q1[v] = qv[il];
-                q2[v] = qv[i];
-                q3[v] = qv[ip1];
-                q4[v] = qv[ip2];
+                q0[v] = sm[v * NT + tm2];
+                q1[v] = sm[v * NT + tl];
+                q3[v] = sm[v * NT + tr];
+                q4[v] = sm[v * NT + tp2];
             }
-            rl = W[rowbase + il];
-            rr = W[rowbase + i];
-            bn = A.bface[rowbase + i];
-            if (ion) {
-                gl = W[8 * N + rowbase + il];
-                gr = W[8 * N + rowbase + i];
-            }
+            rl = sm[6 * NT + tl];
+            if (ION) gl = sm[7 * NT + tl];
 #pragma unroll
             for (int v = 0; v < 6; v++) {
                 dm[v] = limited_slope(q1[v], q2[v], q3[v]);
-                sm[v * NT + tid] = dm[v];
+                sm[(8 + v) * NT + tid] = dm[v];
             }
         }
         __syncthreads();
@@ -271,8 +306,8 @@ struct BFaceXRows {
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                fl[v] = interface_value(q1[v], q2[v], sm[v * NT + tl], dm[v]);
-                sm[(6 + v) * NT + tid] = fl[v];
+                fl[v] = interface_value(q1[v], q2[v], sm[(8 + v) * NT + tl], dm[v]);
+                sm[v * NT + tid] = fl[v];
             }
         }
         __syncthreads();
@@ -283,7 +318,7 @@ struct BFaceXRows {
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                T fr = sm[(6 + v) * NT + tr];
+                T fr = sm[v * NT + tr];
                 Par<T> P = parabola_finish(q0[v], q1[v], q2[v], q3[v], q4[v], fl[v], fr, dm[v]);
                 side_right(P, R, v);
                 pub[3 * v + 0] = P.qR;
@@ -307,27 +342,26 @@ struct BFaceXRows {
         }
         T out[7];
         // parabola variables 3, 4, 5 are Bt1, Bt2, p
-        face_solve(rl, q1[5], q1[3], q1[4], rr, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gr, ion,
+        face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
                    T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
         store_face(A.F, N, rowbase + i, out);
     }
 };
 
 // NONADV faces along D = y or z: each thread marches along one grid line over
-// a segment of `seg` faces with a sliding 5-cell window in registers, so each
-// cell's parabolas are computed once per segment (seg + 1 per seg faces);
-// threads are consecutive in x, so every load is coalesced.
-template <typename T, int D>
+// a segment of `seg` faces with a sliding 5-cell window of primitives in
+// registers, so each cell's primitives and parabolas are formed once per
+// segment (seg + 1 per seg faces); threads are consecutive in x, so every load
+// is coalesced.
+template <typename T, int D, bool ION>
 struct BFaceMarch {
     static constexpr int NT = NTH;
     static constexpr bool XCD = false;
     using Args = FaceArgs<T>;
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
-        using V = Vars<D>;
         const Geo& g = A.g;
         const size_t N = (size_t)g.n;
-        const T* W = A.W;
         const int seg = A.seg;
         const int nd = D == 1 ? g.ny : g.nz;
         const int no = D == 1 ? g.nz : g.ny;
@@ -344,15 +378,26 @@ struct BFaceMarch {
         const int x1 = min(x0 + seg, nd);
         const T gm = T(A.a.gamma);
         const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
+        // offsets of the upper neighbours along t1, t2 (the same for every
+        // cell of the line): y march t1 = z, t2 = x; z march t1 = x, t2 = y
+        const int dxp = (i + 1 == g.nx ? 0 : i + 1) - i;
+        const int dop = ((o + 1 == no ? 0 : o + 1) - o) * (D == 1 ? g.nxy : g.nx);
+        const int o1 = D == 1 ? dop : dxp, o2 = D == 1 ? dxp : dop;
 
-        // window: w[v][m] = variable v of cell x-2+m; v = 0..5 parabola variables, 6 = rho
+        // window: w[v][m] = variable v of cell x-2+m; v = 0..5 parabola
+        // variables, 6 = rho; gw[m] its gamma (network only)
         T w[7][5];
+        T gw[5];
 #pragma unroll
         for (int m = 0; m < 5; m++) {
             int cc = base + wrapc(x0 - 3 + m, nd) * stride;
+            Raw<T> rw;
+            raw_load<T, D, ION>(A.U, cc, cc + o1, cc + o2, rw);
+            T qm[6];
+            raw_prim<T, ION>(rw, A.a.gamma, qm, gw[m]);
 #pragma unroll
-            for (int v = 0; v < 6; v++) w[v][m] = W[(size_t)V::f[v] * N + cc];
-            w[6][m] = W[cc];
+            for (int v = 0; v < 6; v++) w[v][m] = qm[v];
+            w[6][m] = rw.rho;
         }
         // parabolas of cell x0 - 1 (the left side of the first face).  Along
         // the march each cell's limited slope and each face's interface value
@@ -373,18 +418,30 @@ struct BFaceMarch {
             fl[v] = f1;
         }
 
-        // gamma_eff of the face's left cell, carried along the march
-        const bool ion = A.a.ion != 0;
-        T gl = ion ? W[8 * N + base + wrapc(x0 - 1, nd) * stride] : gm;
-        for (int x = x0; x < x1; x++) {
+        // the conserved values of the cell entering the window (x + 2 for
+        // face x) are loaded one face ahead, so the loads are in flight while
+        // the previous face is solved
+        Raw<T> nr;
+        auto fetch = [&](int x) {
             int cn = base + wrapc(x + 2, nd) * stride;
+            raw_load<T, D, ION>(A.U, cn, cn + o1, cn + o2, nr);
+        };
+        fetch(x0);
+        for (int x = x0; x < x1; x++) {
+            T qn[6], gn;
+            raw_prim<T, ION>(nr, A.a.gamma, qn, gn);
 #pragma unroll
             for (int v = 0; v < 7; v++) {
 #pragma unroll
                 for (int m = 0; m < 4; m++) w[v][m] = w[v][m + 1];
-                w[v][4] = W[(size_t)(v < 6 ? V::f[v] : 0) * N + cn];
+                w[v][4] = v < 6 ? qn[v] : nr.rho;
             }
-            const T gr = ion ? W[8 * N + base + x * stride] : gm;
+            if (ION) {
+#pragma unroll
+                for (int m = 0; m < 4; m++) gw[m] = gw[m + 1];
+                gw[4] = gn;
+            }
+            if (x + 1 < x1) fetch(x + 1);
             Side<T> R, Ln;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
@@ -400,11 +457,10 @@ struct BFaceMarch {
             int c = base + x * stride;
             T out[7];
             // left cell x-1 is window slot 1, right cell x is slot 2
-            face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], A.bface[c], L, R,
-                       gm, gl, gr, ion, ydx, out);
+            face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], A.U.f[BX + D][c], L,
+                       R, gm, ION ? gw[1] : gm, ION ? gw[2] : gm, ION, ydx, out);
             store_face(A.F, N, c, out);
             L = Ln;
-            gl = gr;
         }
     }
 };
@@ -416,23 +472,26 @@ struct BFaceMarch {
 // the two edge fields on its upper z edges are the lower ones of cell k+1, so
 // they are carried instead of read or formed again (same arithmetic).
 template <typename T>
+struct NonadvUpdateArgs {
+    Geo g;
+    CFields<T> U, S;
+    Fields<T> O;
+    const T* Fx;
+    const T* Fy;
+    const T* Fz;
+    StepArgs a;
+    RK rk;
+    int dbg;
+    ZTile zt;
+    const T* phi;   // gravitational potential, or null without self-gravity
+};
+
+template <typename T, bool ION>
 struct BNonadvUpdate {
     static constexpr int NT = NTH;
     static constexpr bool XCD = false;
-    struct Args {
-        Geo g;
-        CFields<T> U, S;
-        Fields<T> O;
-        const T* Fx;
-        const T* Fy;
-        const T* Fz;
-        StepArgs a;
-        RK rk;
-        int dbg;
-        ZTile zt;
-        const T* phi;   // gravitational potential, or null without self-gravity
-        const T* gam;   // per-cell gamma_eff (ionisation network), or null
-    };
+    static constexpr int MINW = ION ? 1 : 4;
+    using Args = NonadvUpdateArgs<T>;
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         const Geo& g = A.g;
@@ -458,21 +517,28 @@ struct BNonadvUpdate {
         const T* eyx = Fy + 6 * N;   // y faces, E along x
         const T* exy = Fx + 5 * N;   // x faces, E along y
         const T* exz = Fx + 6 * N;   // x faces, E along z
-        auto Ex = [&](int cc, int cym, int czm) { return T(0.25) * (((ezx[cym] + ezx[cc]) + eyx[cc]) + eyx[czm]); };
-        auto Ey = [&](int cc, int cxm, int czm) { return T(0.25) * (((ezy[cxm] + ezy[cc]) + exy[czm]) + exy[cc]); };
         auto Ez = [&](int cc, int cym, int cxm) { return T(0.25) * (((exz[cym] + exz[cc]) + eyz[cxm]) + eyz[cc]); };
 
-        // carried: z-face values at the lower face of the current cell and the
-        // Ex, Ey on its lower z edges
+        // carried from the cell below: the z-face values at the lower face of
+        // the current cell, the Ex, Ey on its lower z edges, and the face
+        // edge-field values of the current plane (and of the plane below at
+        // x+1, y+1) that the cell below read as its upper-plane values
         T fzc[5];
         T Ex_c, Ey_c;
+        T ezx_c, eyx_c, ezy_c, exy_c, eyx_ypm, exy_xpm;
         {
             int c = i + nx * j + nxy * k0;
             int zm = c + ((k0 == 0 ? nz - 1 : k0 - 1) - k0) * nxy;
 #pragma unroll
             for (int v = 0; v < 5; v++) fzc[v] = Fz[v * N + c];
-            Ex_c = Ex(c, c + dym, zm);
-            Ey_c = Ey(c, c + dxm, zm);
+            ezx_c = ezx[c];
+            eyx_c = eyx[c];
+            ezy_c = ezy[c];
+            exy_c = exy[c];
+            eyx_ypm = eyx[zm + dyp];
+            exy_xpm = exy[zm + dxp];
+            Ex_c = T(0.25) * (((ezx[c + dym] + ezx_c) + eyx_c) + eyx[zm]);
+            Ey_c = T(0.25) * (((ezy[c + dxm] + ezy_c) + exy[zm]) + exy_c);
         }
         const T ra = T(A.rk.a), rb = T(A.rk.b);
         const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
@@ -496,12 +562,20 @@ struct BNonadvUpdate {
             inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
             inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
             T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
-            inc[EI] = -(A.gam ? A.gam[c] - T(1) : T(A.a.gamma - 1.0)) * A.U.f[EI][c] * dtdx * divv;
+            // with the network, gamma_eff of the cell (FP64, as the tail forms it)
+            T gm1 = T(A.a.gamma - 1.0);
+            if (ION)
+                gm1 = T(gamma_cell(1, 0.0, (double)A.U.f[RHO][c], (double)A.U.f[H2][c], (double)A.U.f[HP][c])) - T(1);
+            inc[EI] = -gm1 * A.U.f[EI][c] * dtdx * divv;
 
-            T Ex_yp = Ex(yp, c, yp + dzm);
-            T Ex_zp = Ex(zp, zp + dym, c);
-            T Ey_xp = Ey(xp, c, xp + dzm);
-            T Ey_zp = Ey(zp, zp + dxm, c);
+            // edge fields on the upper edges (Ex, Ey at z+1/2; Ex at y+1/2, Ey
+            // at x+1/2): the same sums as Ex(), Ey() with the carried values
+            const T ezx_zp = ezx[zp], eyx_zp = eyx[zp], ezy_zp = ezy[zp], exy_zp = exy[zp];
+            const T eyx_yp = eyx[yp], exy_xp = exy[xp];
+            T Ex_yp = T(0.25) * (((ezx_c + ezx[yp]) + eyx_yp) + eyx_ypm);
+            T Ex_zp = T(0.25) * (((ezx[zp + dym] + ezx_zp) + eyx_zp) + eyx_c);
+            T Ey_xp = T(0.25) * (((ezy_c + ezy[xp]) + exy_xpm) + exy_xp);
+            T Ey_zp = T(0.25) * (((ezy[zp + dxm] + ezy_zp) + exy_c) + exy_zp);
             T Ez_c = Ez(c, ym, xm);
             T Ez_xp = Ez(xp, xp + dym, c);
             T Ez_yp = Ez(yp, c, yp + dxm);
@@ -530,7 +604,7 @@ struct BNonadvUpdate {
                 for (int q = 0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
                 A.O.f[RHO][c] = T(0);
                 A.O.f[H2][c] = T(0);
-                if (A.gam) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
+                if (ION) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
             } else {
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
@@ -543,6 +617,12 @@ struct BNonadvUpdate {
             for (int v = 0; v < 5; v++) fzc[v] = fzp[v];
             Ex_c = Ex_zp;
             Ey_c = Ey_zp;
+            ezx_c = ezx_zp;
+            eyx_c = eyx_zp;
+            ezy_c = ezy_zp;
+            exy_c = exy_zp;
+            eyx_ypm = eyx_yp;
+            exy_xpm = exy_xp;
         }
     }
 };
@@ -893,22 +973,35 @@ struct BAdvZUpdate {
         };
         T Flo[NQ];
         zflux(w, velocity(), ydx, Flo);
+        // the values cell x needs from beyond the window (cell x+3 entering
+        // it; rho and mz of cell x+1 when the group holds neither) are loaded
+        // one cell ahead, so the loads are in flight during the previous cell
+        constexpr bool own_v = Q0 == 0 && NQ >= 4;   // rho and mz are window fields 0 and 3
+        T nw[NQ], nvr = T(0), nvm = T(0);
+        auto fetch = [&](int x) {
+            int cn = base + wrapc(x + 3, nd) * stride;
+#pragma unroll
+            for (int q = 0; q < NQ; q++) nw[q] = A.U.f[fld[Q0 + q]][cn];
+            if (!own_v) {
+                int c1 = base + wrapc(x + 1, nd) * stride;
+                nvr = A.U.f[RHO][c1];
+                nvm = A.U.f[MZ][c1];
+            }
+        };
+        fetch(x0);
         for (int x = x0; x < x1; x++) {
             // slide: window slots 0..5 = cells x-2 .. x+3
-            int cn = base + wrapc(x + 3, nd) * stride;
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
 #pragma unroll
                 for (int m = 0; m < 5; m++) w[q][m] = w[q][m + 1];
-                w[q][5] = A.U.f[fld[Q0 + q]][cn];
+                w[q][5] = nw[q];
             }
-            {
-                int c1 = base + wrapc(x + 1, nd) * stride;
-                vr[0] = vr[1];
-                vm[0] = vm[1];
-                vr[1] = A.U.f[RHO][c1];
-                vm[1] = A.U.f[MZ][c1];
-            }
+            vr[0] = vr[1];
+            vm[0] = vm[1];
+            vr[1] = own_v ? w[0][3] : nvr;
+            vm[1] = own_v ? w[3][3] : nvm;
+            if (x + 1 < x1) fetch(x + 1);
             // upper face of cell x: between slots 2 (cell x) and 3 (cell x+1)
             T Fup[NQ];
             zflux(w, velocity(), ydx, Fup);
