@@ -34,9 +34,14 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per cell for one launch of each kernel class, in
 # stored values (x 8 B for FP64, x 4 B for FP32): the fields the kernel must
 # read once and write once, with neighbour re-reads excluded
+# NONADV face class, per launch averaged over its three launches: the y and z
+# face kernels read rho, m(3), e, 2 transverse b and the face b_n and write 7
+# face outputs; the x-row kernel also updates m, E, e: it reads those 8 fields,
+# the y and z face fluxes (5 each), E and Q0 of m, E, e (6), and writes m, E, e
+# and the two edge-field components of its faces
 ALG_VALUES = {
-    "nonadv_face": 8 + 7,     # rho, m(3), e, 2 transverse b, face b_n -> 7 face outputs
-    "nonadv_update": 21 + 8 + 8 + 8,   # 3 x 7 face outputs, U and Q0 (8 fields each) -> 8 fields
+    "nonadv_face": ((8 + 5 + 5 + 6) + (5 + 2) + 2 * (8 + 7)) / 3,
+    "nonadv_update": 6 + 3 + 3 + 3,    # 6 edge-field components, b and Q0 of b (3 each) -> b
     "adv_face": 7 + 7,        # 7 advected fields -> 7 fluxes
     "adv_update": 21 + 7 + 7 + 7,      # 3 x 7 fluxes, U, Q0 -> 7 fields
     "tail": 10 + 2,           # state -> h2, e
@@ -89,8 +94,12 @@ def _timed_run(box, steps, dts=None):
 # limited slope (11), one interface value (5) and the Steps 2-5 finish (70);
 # then the face solve: averaged state 20, eigen-structure 55, the 32 parabola
 # averages the waves read 140, characteristic amplitudes 97, projector sum 49,
-# fluxes and edge-field terms 24
-ALG_FLOPS = {"nonadv_face": 6 * (11 + 5 + 70) + (20 + 55 + 140 + 97 + 49 + 24)}
+# fluxes and edge-field terms 24.  The x launch also updates m, E, e: 15 flux
+# differences, 17 for the increments and the p dV term, 25 for the
+# Runge-Kutta combination of five fields; the class figure is per launch,
+# averaged over its three launches.
+FACE_FLOPS = 6 * (11 + 5 + 70) + (20 + 55 + 140 + 97 + 49 + 24)
+ALG_FLOPS = {"nonadv_face": (3 * FACE_FLOPS + (15 + 17 + 25)) / 3}
 # published MI355X vector peaks (TFLOP/s) and HBM peak
 VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 
@@ -117,7 +126,7 @@ def _kernel_source_hash():
 def _roofline(timing, ncell, esz, workload):
     name, (ms, cnt) = max(((k, v) for k, v in timing.items() if k in ALG_VALUES), key=lambda kv: kv[1][0])
     avg_s = ms / cnt / 1e3
-    alg_bytes = ALG_VALUES[name] * esz * ncell
+    alg_bytes = int(round(ALG_VALUES[name] * esz * ncell))
     gbs = alg_bytes / avg_s / 1e9
     tr = TRAFFIC.get((workload, esz, name))
     traffic = tr[1] if tr is not None and tr[0] == _kernel_source_hash() else None
@@ -128,7 +137,7 @@ def _roofline(timing, ncell, esz, workload):
         # one face per cell per launch
         tf = ALG_FLOPS[name] * ncell / avg_s / 1e12
         out.update({"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TF[esz], "unit": "TFLOP/s",
-                    "frac": round(tf / VALU_PEAK_TF[esz], 4), "alg_flops_per_launch": ALG_FLOPS[name] * ncell})
+                    "frac": round(tf / VALU_PEAK_TF[esz], 4), "alg_flops_per_launch": int(round(ALG_FLOPS[name] * ncell))})
     else:
         out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4)})

@@ -356,42 +356,57 @@ struct MultiEmit {
 
 // ---------------------------------------------------------------- the step program
 
-template <typename T, bool ION, class Emit>
-void emit_nonadv_faces_t(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a, bool first)
+// z cells per thread in the z-marching update kernels
+constexpr int ZMARCH_SEG = 32;
+
+// tiles of the z-marching update kernels: 64 x cells (a wave) by nt / 64
+// rows for blocks of nt threads, narrower for thin boxes
+ZTile ztile_of(const Geo& g, int nt = NTH)
 {
+    ZTile z;
+    z.tx = g.nx < 64 ? g.nx : 64;
+    z.ty = nt / z.tx;
+    z.ntx = (g.nx + z.tx - 1) / z.tx;
+    z.nty = (g.ny + z.ty - 1) / z.ty;
+    z.seg = g.nz < ZMARCH_SEG ? g.nz : ZMARCH_SEG;
+    return z;
+}
+
+int ztile_blocks(const Geo& g, const ZTile& z)
+{
+    return z.ntx * z.nty * ((g.nz + z.seg - 1) / z.seg);
+}
+
+// One NONADV substage.  y and z faces first (marching kernels); then, for
+// boxes whose x rows fit a block, the x-row face kernel, which also updates
+// m, E and e, and the face-field update; otherwise the one-face-per-thread x
+// kernel and the full update.  The primitives are formed inside the face
+// kernels from the substage input state.
+template <typename T, bool ION, class Emit>
+void emit_nonadv_substage_t(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk,
+                            int dbg, bool first)
+{
+    Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
+    Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
+    Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
     const Geo& g = b->g;
     T* F0 = reinterpret_cast<T*>(b->F[0]);
     T* F1 = reinterpret_cast<T*>(b->F[1]);
     T* F2 = reinterpret_cast<T*>(b->F[2]);
-    FaceArgs<T> fa;
+    const T* phi = b->grav ? reinterpret_cast<const T*>(b->phi) : nullptr;
+    FaceArgs<T> fa{};
     fa.g = g;
     fa.U = cview(in);
     fa.a = a;
     fa.flags = b->flags;
-    // the x-face launch of the first substage checks an explicit dt against
-    // the last device CFL bound
-    fa.dt_cfl = first ? b->dt_dev : nullptr;
-    // x faces: whole rows per block when a row fits one block, else one face per thread
-    fa.F = F0;
-    const int maxt = sizeof(T) == 8 ? 512 : 1024;
-    if (g.nx <= maxt) {
-        int rpb = g.nx >= 256 ? 1 : 256 / g.nx;
-        int rows = g.ny * g.nz;
-        fa.rpb = rpb;
-        fa.seg = 0;
-        int blocks = (rows + rpb - 1) / rpb;
-        if (g.nx <= 256)
-            e.template launch<BFaceXRows<T, 256, ION>>(MHD_K_NONADV_FACE, blocks, 256 * 18 * sizeof(T), fa);
-        else if (g.nx <= 512)
-            e.template launch<BFaceXRows<T, 512, ION>>(MHD_K_NONADV_FACE, blocks, 512 * 18 * sizeof(T), fa);
-        else if constexpr (sizeof(T) == 4)   // 1024-thread rows only in FP32 (register budget)
-            e.template launch<BFaceXRows<T, 1024, ION>>(MHD_K_NONADV_FACE, blocks, 1024 * 18 * sizeof(T), fa);
-    } else {
-        fa.rpb = 0;
-        fa.seg = 0;
-        e.template launch<BFacePair<T, 0, ION>>(MHD_K_NONADV_FACE, b->nblocks, 0, fa);
-    }
     fa.dt_cfl = nullptr;
+    fa.S = cview(S);
+    fa.O = out;
+    fa.Fy = F1;
+    fa.Fz = F2;
+    fa.rk = rk;
+    fa.dbg = dbg;
+    fa.phi = phi;
     // y and z faces: marching segments
     constexpr int MARCH_SEG = 32;
     for (int D = 1; D <= 2; D++) {
@@ -407,65 +422,55 @@ void emit_nonadv_faces_t(mhd_box* b, Emit& e, const Fields<T>& in, const StepArg
         else
             e.template launch<BFaceMarch<T, 2, ION>>(MHD_K_NONADV_FACE, blocks, 0, fa);
     }
-}
-
-// NONADV faces of the three directions; the primitives are formed inside the
-// face kernels from the substage input state
-template <typename T, class Emit>
-void emit_nonadv_faces(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a, bool first)
-{
-    if (b->p.ionisation)
-        emit_nonadv_faces_t<T, true>(b, e, in, a, first);
+    // x faces; the launch of the first substage checks an explicit dt
+    // against the last device CFL bound
+    fa.F = F0;
+    fa.seg = 0;
+    fa.dt_cfl = first ? b->dt_dev : nullptr;
+    const int maxt = sizeof(T) == 8 ? 512 : 1024;
+    const bool rows = g.nx <= maxt;
+    if (rows) {
+        int rpb = g.nx >= 256 ? 1 : 256 / g.nx;
+        fa.rpb = rpb;
+        int blocks = (g.ny * g.nz + rpb - 1) / rpb;
+        if (g.nx <= 256)
+            e.template launch<BFaceXRows<T, 256, ION>>(MHD_K_NONADV_FACE, blocks, 256 * 18 * sizeof(T), fa);
+        else if (g.nx <= 512)
+            e.template launch<BFaceXRows<T, 512, ION>>(MHD_K_NONADV_FACE, blocks, 512 * 18 * sizeof(T), fa);
+        else if constexpr (sizeof(T) == 4)   // 1024-thread rows only in FP32 (register budget)
+            e.template launch<BFaceXRows<T, 1024, ION>>(MHD_K_NONADV_FACE, blocks, 1024 * 18 * sizeof(T), fa);
+    } else {
+        fa.rpb = 0;
+        e.template launch<BFacePair<T, 0, ION>>(MHD_K_NONADV_FACE, b->nblocks, 0, fa);
+    }
+    NonadvUpdateArgs<T> ua;
+    ua.g = g;
+    ua.U = cview(in);
+    ua.S = cview(S);
+    ua.O = out;
+    ua.Fx = F0;
+    ua.Fy = F1;
+    ua.Fz = F2;
+    ua.a = a;
+    ua.rk = rk;
+    ua.dbg = dbg;
+    ua.zt = ztile_of(g, UPD_NT);
+    ua.phi = phi;
+    const int ublocks = ztile_blocks(g, ua.zt);
+    if (rows)
+        e.template launch<BNonadvUpdate<T, ION, false>>(MHD_K_NONADV_UPDATE, ublocks, 0, ua);
     else
-        emit_nonadv_faces_t<T, false>(b, e, in, a, first);
-}
-
-// z cells per thread in the z-marching update kernels
-constexpr int ZMARCH_SEG = 32;
-
-// tiles of the z-marching update kernels: 64 x cells (a wave) by NTH / 64
-// rows, narrower for thin boxes
-ZTile ztile_of(const Geo& g)
-{
-    ZTile z;
-    z.tx = g.nx < 64 ? g.nx : 64;
-    z.ty = NTH / z.tx;
-    z.ntx = (g.nx + z.tx - 1) / z.tx;
-    z.nty = (g.ny + z.ty - 1) / z.ty;
-    z.seg = g.nz < ZMARCH_SEG ? g.nz : ZMARCH_SEG;
-    return z;
-}
-
-int ztile_blocks(const Geo& g, const ZTile& z)
-{
-    return z.ntx * z.nty * ((g.nz + z.seg - 1) / z.seg);
+        e.template launch<BNonadvUpdate<T, ION, true>>(MHD_K_NONADV_UPDATE, ublocks, 0, ua);
 }
 
 template <typename T, class Emit>
 void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg,
                           bool first)
 {
-    Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
-    Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
-    Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
-    emit_nonadv_faces<T>(b, e, in, a, first);
-    NonadvUpdateArgs<T> ua;
-    ua.g = b->g;
-    ua.U = cview(in);
-    ua.S = cview(S);
-    ua.O = out;
-    ua.Fx = reinterpret_cast<T*>(b->F[0]);
-    ua.Fy = reinterpret_cast<T*>(b->F[1]);
-    ua.Fz = reinterpret_cast<T*>(b->F[2]);
-    ua.a = a;
-    ua.rk = rk;
-    ua.dbg = dbg;
-    ua.zt = ztile_of(b->g);
-    ua.phi = b->grav ? reinterpret_cast<const T*>(b->phi) : nullptr;
     if (b->p.ionisation)
-        e.template launch<BNonadvUpdate<T, true>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
+        emit_nonadv_substage_t<T, true>(b, e, sin, sS, sout, a, rk, dbg, first);
     else
-        e.template launch<BNonadvUpdate<T, false>>(MHD_K_NONADV_UPDATE, ztile_blocks(b->g, ua.zt), 0, ua);
+        emit_nonadv_substage_t<T, false>(b, e, sin, sS, sout, a, rk, dbg, first);
 }
 
 template <typename T, int D, int NQ, class Emit>

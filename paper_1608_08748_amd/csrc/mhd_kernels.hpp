@@ -173,6 +173,16 @@ struct FaceArgs {
     int seg;                 // faces per thread (marching kernel)
     uint32_t* flags;
     const double* dt_cfl;    // non-null: check the explicit dt against this CFL bound
+    // the x-row kernel also updates m, E, e (the NONADV update of Sec. 2.2,
+    // 2.5 without the face fields): Runge-Kutta inputs and output, the y and
+    // z face outputs, and the gravitational potential (null without gravity)
+    CFields<T> S;
+    Fields<T> O;
+    const T* Fy;
+    const T* Fz;
+    RK rk;
+    int dbg;                 // 1: write tau R(U) instead of the combination
+    const T* phi;
 };
 
 // an explicit dt above the device CFL bound (with its relative slack) latches
@@ -233,12 +243,18 @@ struct BFacePair {
     }
 };
 
-// NONADV faces along x with whole x rows per block: each thread owns one cell,
-// forms its primitives and computes, once each, its limited slopes, the
-// interface values at its lower face and its parabolas (Sec. 2.1);
-// neighbours' primitives, slopes, interface values and parabola sides come
-// through LDS (periodic wrap inside the row).  Dynamic LDS: 18 x NT values,
-// value k of thread t at k * NT + t, reused by the four exchanges.
+// NONADV faces along x with whole x rows per block, fused with the update of
+// m, E and e.  Each thread owns one cell, forms its primitives and computes,
+// once each, its limited slopes, the interface values at its lower face and
+// its parabolas (Sec. 2.1); neighbours' primitives, slopes, interface values
+// and parabola sides come through LDS (periodic wrap inside the row).  After
+// the face solve the row's x-face fluxes are exchanged the same way, so the
+// thread forms the flux differences of its cell (y and z faces from the face
+// kernels that ran before), the p dV work, the gravity sources and the
+// Runge-Kutta combination of m, E, e (Sec. 2.2).  Only the edge-field
+// components of the x faces are stored, for the face-field update.  Dynamic
+// LDS: 18 x NT values, value k of thread t at k * NT + t, reused by the five
+// exchanges.
 template <typename T, int MAXT, bool ION>
 struct BFaceXRows {
     static constexpr int NT = MAXT;
@@ -256,22 +272,23 @@ struct BFaceXRows {
         int i = tid - r * nx;
         int row = blk * A.rpb + r;
         bool act = r < A.rpb && row < g.ny * g.nz;
-        int rowbase = row * nx;
+        const int rowbase = row * nx;
+        const int c = rowbase + i;
         const int rb = r * nx;
         const int tl = rb + (i == 0 ? nx - 1 : i - 1);   // thread of the left cell
         const int tr = rb + (i + 1 == nx ? 0 : i + 1);   // thread of the right cell
         const int tm2 = rb + wrapc(i - 2, nx), tp2 = rb + wrapc(i + 2, nx);
         const T gm = T(A.a.gamma);
+        // periodic offsets of the upper neighbours along y and z
+        const int j = row % g.ny, k = row / g.ny;
+        const int dyp = ((j + 1 == g.ny ? 0 : j + 1) - j) * nx;
+        const int dzp = ((k + 1 == g.nz ? 0 : k + 1) - k) * g.nxy;
 
-        // own cell: conserved values (every global load of the thread), primitives
+        // own cell: conserved values, primitives
         T q2[6], rho = T(0), gam = gm, bn = T(0);
         if (act) {
-            int j = row % g.ny, k = row / g.ny;
-            int c = rowbase + i;
-            int c1 = c + ((j + 1 == g.ny ? 0 : j + 1) - j) * nx;
-            int c2 = c + ((k + 1 == g.nz ? 0 : k + 1) - k) * g.nxy;
             Raw<T> rw;
-            raw_load<T, 0, ION>(A.U, c, c1, c2, rw);
+            raw_load<T, 0, ION>(A.U, c, c + dyp, c + dzp, rw);
             bn = A.U.f[BX][c];
             raw_prim<T, ION>(rw, A.a.gamma, q2, gam);
             rho = rw.rho;
@@ -329,22 +346,89 @@ struct BFaceXRows {
         __syncthreads();
         if (act) {
 #pragma unroll
-            for (int k = 0; k < 18; k++) sm[k * NT + tid] = pub[k];
+            for (int q = 0; q < 18; q++) sm[q * NT + tid] = pub[q];
+        }
+        __syncthreads();
+        T out[7];
+        if (act) {
+            Side<T> L;
+#pragma unroll
+            for (int v = 0; v < 6; v++) {
+                L.e[v] = sm[(3 * v + 0) * NT + tl];
+                L.dq[v] = sm[(3 * v + 1) * NT + tl];
+                L.q6[v] = sm[(3 * v + 2) * NT + tl];
+            }
+            // parabola variables 3, 4, 5 are Bt1, Bt2, p
+            face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
+                       T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+            A.F[5 * N + c] = out[5];
+            A.F[6 * N + c] = out[6];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < 5; v++) sm[v * NT + tid] = out[v];
         }
         __syncthreads();
         if (!act) return;
-        Side<T> L;
+
+        // update of m, E, e: flux differences of the x faces (the right
+        // cell's lower face from LDS), y and z faces (memory)
+        const T dtdx = T(step_dt(A.a) / A.a.h);
+        const T* Fy = A.Fy;
+        const T* Fz = A.Fz;
+        T dF[3][5];
 #pragma unroll
-        for (int v = 0; v < 6; v++) {
-            L.e[v] = sm[(3 * v + 0) * NT + tl];
-            L.dq[v] = sm[(3 * v + 1) * NT + tl];
-            L.q6[v] = sm[(3 * v + 2) * NT + tl];
+        for (int v = 0; v < 5; v++) {
+            dF[0][v] = sm[v * NT + tr] - out[v];
+            dF[1][v] = Fy[v * N + c + dyp] - Fy[v * N + c];
+            dF[2][v] = Fz[v * N + c + dzp] - Fz[v * N + c];
         }
-        T out[7];
-        // parabola variables 3, 4, 5 are Bt1, Bt2, p
-        face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
-                   T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
-        store_face(A.F, N, rowbase + i, out);
+        T inc[5];
+        // momentum component a takes slot (a - d) mod 3 from direction d
+        inc[0] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
+        inc[1] = -dtdx * ((dF[0][1] + dF[1][0]) + dF[2][2]);
+        inc[2] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
+        inc[3] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
+        T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
+        // (gamma - 1) e, with the cell's gamma_eff under the network
+        const T gm1 = ION ? gam - T(1) : T(A.a.gamma - 1.0);
+        inc[4] = -gm1 * A.U.f[EI][c] * dtdx * divv;
+        if (A.phi) {
+            // self-gravity (Sec. 2 equations, Sec. 2.4): -rho grad(Phi) on
+            // m and -m . grad(Phi) on E, central differences
+            const T* ph = A.phi;
+            const T i2h = T(0.5 / A.a.h);
+            const T dt = T(step_dt(A.a));
+            const int dxp = tr - tid, dxm = tl - tid;
+            const int dym = ((j == 0 ? g.ny - 1 : j - 1) - j) * nx;
+            const int dzm = ((k == 0 ? g.nz - 1 : k - 1) - k) * g.nxy;
+            T gv[3] = { (ph[c + dxp] - ph[c + dxm]) * i2h, (ph[c + dyp] - ph[c + dym]) * i2h,
+                        (ph[c + dzp] - ph[c + dzm]) * i2h };
+            T work = T(0);
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                inc[a] -= dt * rho * gv[a];
+                work += A.U.f[MX + a][c] * gv[a];
+            }
+            inc[3] -= dt * work;
+        }
+        const int upd[5] = { MX, MY, MZ, EN, EI };
+        if (A.dbg) {
+#pragma unroll
+            for (int q = 0; q < 5; q++) A.O.f[upd[q]][c] = inc[q];
+            A.O.f[RHO][c] = T(0);
+            A.O.f[H2][c] = T(0);
+            if (ION) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
+        } else {
+            const T ra = T(A.rk.a), rb = T(A.rk.b);
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                int f = upd[q];
+                T u = A.U.f[f][c];
+                A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc[q];
+            }
+        }
     }
 };
 
@@ -486,9 +570,15 @@ struct NonadvUpdateArgs {
     const T* phi;   // gravitational potential, or null without self-gravity
 };
 
-template <typename T, bool ION>
+// threads per block of the NONADV update (its x-y tile is 64 x UPD_NT / 64)
+constexpr int UPD_NT = 256;
+
+// FULL: all eight fields (the update of boxes whose x faces come from the
+// one-face-per-thread kernel); otherwise only the face fields b_x, b_y, b_z,
+// after the x-row face kernel has updated m, E and e
+template <typename T, bool ION, bool FULL>
 struct BNonadvUpdate {
-    static constexpr int NT = NTH;
+    static constexpr int NT = UPD_NT;
     static constexpr bool XCD = false;
     static constexpr int MINW = ION ? 1 : 4;
     using Args = NonadvUpdateArgs<T>;
@@ -529,8 +619,10 @@ struct BNonadvUpdate {
         {
             int c = i + nx * j + nxy * k0;
             int zm = c + ((k0 == 0 ? nz - 1 : k0 - 1) - k0) * nxy;
+            if (FULL) {
 #pragma unroll
-            for (int v = 0; v < 5; v++) fzc[v] = Fz[v * N + c];
+                for (int v = 0; v < 5; v++) fzc[v] = Fz[v * N + c];
+            }
             ezx_c = ezx[c];
             eyx_c = eyx[c];
             ezy_c = ezy[c];
@@ -541,35 +633,55 @@ struct BNonadvUpdate {
             Ey_c = T(0.25) * (((ezy[c + dxm] + ezy_c) + exy[zm]) + exy_c);
         }
         const T ra = T(A.rk.a), rb = T(A.rk.b);
-        const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
         for (int k = k0; k < k1; k++) {
             const int c = i + nx * j + nxy * k;
             const int dzp = ((k + 1 == nz ? 0 : k + 1) - k) * nxy;
             const int dzm = ((k == 0 ? nz - 1 : k - 1) - k) * nxy;
             const int xp = c + dxp, xm = c + dxm, yp = c + dyp, ym = c + dym, zp = c + dzp;
-            T dF[3][5], fzp[5];
-#pragma unroll
-            for (int v = 0; v < 5; v++) {
-                dF[0][v] = Fx[v * N + xp] - Fx[v * N + c];
-                dF[1][v] = Fy[v * N + yp] - Fy[v * N + c];
-                fzp[v] = Fz[v * N + zp];
-                dF[2][v] = fzp[v] - fzc[v];
-            }
             T inc[NF];
-            // momentum component a takes slot (a - d) mod 3 from direction d
-            inc[MX] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
-            inc[MY] = -dtdx * ((dF[0][1] + dF[1][0]) + dF[2][2]);
-            inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
-            inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
-            T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
-            // with the network, gamma_eff of the cell (FP64, as the tail forms it)
-            T gm1 = T(A.a.gamma - 1.0);
-            if (ION)
-                gm1 = T(gamma_cell(1, 0.0, (double)A.U.f[RHO][c], (double)A.U.f[H2][c], (double)A.U.f[HP][c])) - T(1);
-            inc[EI] = -gm1 * A.U.f[EI][c] * dtdx * divv;
+            if (FULL) {
+                T dF[3][5], fzp[5];
+#pragma unroll
+                for (int v = 0; v < 5; v++) {
+                    dF[0][v] = Fx[v * N + xp] - Fx[v * N + c];
+                    dF[1][v] = Fy[v * N + yp] - Fy[v * N + c];
+                    fzp[v] = Fz[v * N + zp];
+                    dF[2][v] = fzp[v] - fzc[v];
+                }
+                // momentum component a takes slot (a - d) mod 3 from direction d
+                inc[MX] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
+                inc[MY] = -dtdx * ((dF[0][1] + dF[1][0]) + dF[2][2]);
+                inc[MZ] = -dtdx * ((dF[0][2] + dF[1][1]) + dF[2][0]);
+                inc[EN] = -dtdx * ((dF[0][3] + dF[1][3]) + dF[2][3]);
+                T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
+                // with the network, gamma_eff of the cell (FP64, as the tail forms it)
+                T gm1 = T(A.a.gamma - 1.0);
+                if (ION)
+                    gm1 = T(gamma_cell(1, 0.0, (double)A.U.f[RHO][c], (double)A.U.f[H2][c], (double)A.U.f[HP][c])) -
+                          T(1);
+                inc[EI] = -gm1 * A.U.f[EI][c] * dtdx * divv;
+                if (A.phi) {
+                    // self-gravity (Sec. 2 equations, Sec. 2.4): -rho grad(Phi) on
+                    // m and -m . grad(Phi) on E, central differences
+                    const T* ph = A.phi;
+                    const T i2h = T(0.5 / A.a.h);
+                    const T dt = T(step_dt(A.a));
+                    T gv[3] = { (ph[xp] - ph[xm]) * i2h, (ph[yp] - ph[ym]) * i2h, (ph[zp] - ph[c + dzm]) * i2h };
+                    T rho = A.U.f[RHO][c];
+                    T work = T(0);
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        inc[MX + a] -= dt * rho * gv[a];
+                        work += A.U.f[MX + a][c] * gv[a];
+                    }
+                    inc[EN] -= dt * work;
+                }
+#pragma unroll
+                for (int v = 0; v < 5; v++) fzc[v] = fzp[v];
+            }
 
             // edge fields on the upper edges (Ex, Ey at z+1/2; Ex at y+1/2, Ey
-            // at x+1/2): the same sums as Ex(), Ey() with the carried values
+            // at x+1/2): the same sums as for the carried lower edges
             const T ezx_zp = ezx[zp], eyx_zp = eyx[zp], ezy_zp = ezy[zp], exy_zp = exy[zp];
             const T eyx_yp = eyx[yp], exy_xp = exy[xp];
             T Ex_yp = T(0.25) * (((ezx_c + ezx[yp]) + eyx_yp) + eyx_ypm);
@@ -582,39 +694,25 @@ struct BNonadvUpdate {
             inc[BX] = -dtdx * (Ez_yp - Ez_c) + dtdx * (Ey_zp - Ey_c);
             inc[BY] = -dtdx * (Ex_zp - Ex_c) + dtdx * (Ez_xp - Ez_c);
             inc[BZ] = -dtdx * (Ey_xp - Ey_c) + dtdx * (Ex_yp - Ex_c);
-            if (A.phi) {
-                // self-gravity (Sec. 2 equations, Sec. 2.4): -rho grad(Phi) on
-                // m and -m . grad(Phi) on E, central differences
-                const T* ph = A.phi;
-                const T i2h = T(0.5 / A.a.h);
-                const T dt = T(step_dt(A.a));
-                T gv[3] = { (ph[xp] - ph[xm]) * i2h, (ph[yp] - ph[ym]) * i2h, (ph[zp] - ph[c + dzm]) * i2h };
-                T rho = A.U.f[RHO][c];
-                T work = T(0);
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    inc[MX + a] -= dt * rho * gv[a];
-                    work += A.U.f[MX + a][c] * gv[a];
-                }
-                inc[EN] -= dt * work;
-            }
 
+            constexpr int Q0 = FULL ? 0 : 5;
+            const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
             if (A.dbg) {
 #pragma unroll
-                for (int q = 0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
-                A.O.f[RHO][c] = T(0);
-                A.O.f[H2][c] = T(0);
-                if (ION) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
+                for (int q = Q0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
+                if (FULL) {
+                    A.O.f[RHO][c] = T(0);
+                    A.O.f[H2][c] = T(0);
+                    if (ION) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
+                }
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; q++) {
+                for (int q = Q0; q < 8; q++) {
                     int f = upd[q];
                     T u = A.U.f[f][c];
                     A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc[f];
                 }
             }
-#pragma unroll
-            for (int v = 0; v < 5; v++) fzc[v] = fzp[v];
             Ex_c = Ex_zp;
             Ey_c = Ey_zp;
             ezx_c = ezx_zp;
