@@ -422,12 +422,16 @@ struct BFaceXRows {
             if (ION) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
         } else {
             const T ra = T(A.rk.a), rb = T(A.rk.b);
+            // all loads before the first store (outputs may alias inputs as
+            // far as the compiler knows)
+            T uv[5], sv[5];
 #pragma unroll
             for (int q = 0; q < 5; q++) {
-                int f = upd[q];
-                T u = A.U.f[f][c];
-                A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc[q];
+                uv[q] = A.U.f[upd[q]][c];
+                sv[q] = A.S.f[upd[q]][c];
             }
+#pragma unroll
+            for (int q = 0; q < 5; q++) A.O.f[upd[q]][c] = (uv[q] + ra * (sv[q] - uv[q])) + rb * inc[q];
         }
     }
 };
@@ -975,7 +979,7 @@ struct BAdvFace {
         T vf = (A.U.f[MX + D][idx[2]] * rsl + A.U.f[MX + D][c] * rsr) * rcp_nr(rl * rsl + rr * rsr);
         bool upw = vf >= T(0);
         T y = upw ? ydx * vf : ydx * (-vf);
-                const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
+        const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
             const T* u = A.U.f[fld[q]];
@@ -1100,25 +1104,34 @@ struct BAdvZUpdate {
             vr[1] = own_v ? w[0][3] : nvr;
             vm[1] = own_v ? w[3][3] : nvm;
             if (x + 1 < x1) fetch(x + 1);
-            // upper face of cell x: between slots 2 (cell x) and 3 (cell x+1)
-            T Fup[NQ];
-            zflux(w, velocity(), ydx, Fup);
+            // the cell's x/y flux differences and Runge-Kutta input, loaded
+            // before the z flux is formed so the loads overlap it, and before
+            // any store (the output fields may alias the inputs as far as the
+            // compiler knows)
             int c = base + x * stride;
             int cxp = c - i + ip;
             int cyp = c + (jp - j) * g.nx;
+            T dx[NQ], dy[NQ], sv[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 const size_t o = (size_t)(Q0 + q) * N;
-                T dx = A.Fx[o + cxp] - A.Fx[o + c];
-                T dy = A.Fy[o + cyp] - A.Fy[o + c];
+                dx[q] = A.Fx[o + cxp] - A.Fx[o + c];
+                dy[q] = A.Fy[o + cyp] - A.Fy[o + c];
+                sv[q] = A.S.f[fld[Q0 + q]][c];
+            }
+            // upper face of cell x: between slots 2 (cell x) and 3 (cell x+1)
+            T Fup[NQ];
+            zflux(w, velocity(), ydx, Fup);
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
                 T dz = Fup[q] - Flo[q];
-                T inc = -dtdx * ((dx + dy) + dz);
+                T inc = -dtdx * ((dx[q] + dy[q]) + dz);
                 int f = fld[Q0 + q];
                 if (A.dbg) {
                     A.O.f[f][c] = inc;
                 } else {
                     T u = w[q][2];
-                    A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc;
+                    A.O.f[f][c] = (u + ra * (sv[q] - u)) + rb * inc;
                 }
                 Flo[q] = Fup[q];
             }
