@@ -109,8 +109,9 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 # by 2 and WRITE_SIZE by 1, the factors that make a 1 GiB device copy read and
 # write 1 GiB
 TRAFFIC = {
-    # average of the x-row, y-march and z-march face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("e464a7d7fe22b806", 2105771349),
+    # average of the x-row (with the m, E, e update), y-march and z-march
+    # face kernels, bytes per launch
+    ("c2", 8, "nonadv_face"): ("4d4e6b109fcb0aa6", 3309743947),
 }
 
 
