@@ -3,8 +3,9 @@
     python bench.py [--config c2] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 A step is one full pass of the method over the box: NONADV stage (3 RK
-substages: primitive pass, face Riemann solves along x, y, z, flux / edge-field
-update), ADV stage (3 RK substages: face fluxes along x, y, z, update), tail
+substages: face Riemann solves along y, z, then x fused with the update of
+m, E, e, then the face-field update from edge fields), ADV stage (3 RK
+substages: face fluxes along x, y, then z fused with the update), tail
 (H2 clamp, FP64 chemistry, FP64 regularisation, CFL speed) and the CFL
 reduction.  The timed region is K x {dt = cfl_dt(); step(dt)} with the state
 resident in HBM, bracketed by device synchronisation.
@@ -14,7 +15,7 @@ Workloads (synthetic, seeded; see paper_1608_08748_amd/inputs.py):
   c3  512^3 FP32 state (FP64 chemistry / reductions), rms Mach 5, beta 0.3,
       seed 3, with the FP64 run of the same seed and dt sequence for the error
   c1  32^3 FP64 white-noise box (the oracle's own configuration)
-  c4  1024^3 FP32 single box (about 253 GB of HBM), conservation over the run
+  c4  1024^3 FP32 single box (about 237 GB of HBM), conservation over the run
   c5  serving: 256 boxes of {32..128}^3 with Poisson arrivals, p50/p99 latency
 
 Prints one JSON line.
