@@ -222,7 +222,7 @@ def _serving_bench(args):
 
 
 def _largest_box_bench(args):
-    """c4: one 1024^3 FP32 box (three state copies of 10 fields = 129 GB plus
+    """c4: one 1024^3 FP32 box (three state copies of 11 fields = 142 GB plus
     scratch, about 237 GB of HBM), lognormal density, rms Mach 10, beta 0.1.
     There is no FP64 twin at this size (it would need twice the memory); the
     full-size checks are the properties that hold at any size: conservation of
