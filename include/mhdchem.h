@@ -234,6 +234,12 @@ typedef struct {
     int32_t steps;           /* steps to run                                      */
     int32_t keep_state;      /* 1: keep the final conserved state for           */
                              /*    mhd_server_result                              */
+    int32_t borrow;          /* 0: the primitive state is copied at submission;  */
+                             /* 1: it is read in place when the request is       */
+                             /*    admitted: the caller keeps it valid and       */
+                             /*    unchanged until mhd_server_poll has returned  */
+                             /*    the request's completion (no host copy; from  */
+                             /*    pinned host memory the upload is one DMA)     */
 } mhd_request;
 
 typedef struct {
@@ -259,8 +265,9 @@ size_t mhd_server_box_bytes(const mhd_server_params *p, const int32_t n[3]);
 int mhd_server_create(const mhd_server_params *p, mhd_server **out);
 
 /* Queue a request with its primitive initial state (host FP64, the
- * mhd_init_state layout; copied).  MHD_ENOMEM if the box can never fit the
- * pool, MHD_EINVAL for bad sizes.  Does not touch the device. */
+ * mhd_init_state layout; copied, or borrowed with r->borrow = 1).  MHD_ENOMEM
+ * if the box can never fit the pool, MHD_EINVAL for bad sizes or flags.  Does
+ * not touch the device. */
 int mhd_server_submit(mhd_server *s, const mhd_request *r, const double *prim, uint64_t *id);
 
 /* Admit queued requests while a slot and pool memory are free (first come,
@@ -273,7 +280,7 @@ int mhd_server_progress(mhd_server *s, int *n_active, int *n_pending);
 int mhd_server_poll(mhd_server *s, mhd_completion *out, int cap, int *n);
 
 /* Copy the final conserved state (MHD_NFIELDS fields, host FP64) of a finished request
- * submitted with keep_state = 1; count must be 10 * cells.  Once per request. */
+ * submitted with keep_state = 1; count must be MHD_NFIELDS * cells.  Once per request. */
 int mhd_server_result(mhd_server *s, uint64_t id, double *cons_out, size_t count);
 
 /* Pool bytes in use now, the peak so far, and the pool size. */

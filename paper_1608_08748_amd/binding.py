@@ -68,7 +68,8 @@ class ServerParams(ctypes.Structure):
 
 
 class Request(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32 * 3), ("steps", ctypes.c_int32), ("keep_state", ctypes.c_int32)]
+    _fields_ = [("n", ctypes.c_int32 * 3), ("steps", ctypes.c_int32), ("keep_state", ctypes.c_int32),
+                ("borrow", ctypes.c_int32)]
 
 
 class Completion(ctypes.Structure):
@@ -314,21 +315,28 @@ class Server:
         _check(lib().mhd_server_create(ctypes.byref(self.p), ctypes.byref(h)), "mhd_server_create")
         self.h = h
         self.shapes = {}
+        self.held = {}      # borrowed request states, kept alive until their completion is polled
 
     def box_bytes(self, shape):
         return server_box_bytes(self.p, shape)
 
-    def submit(self, W, steps, keep_state=False):
+    def submit(self, W, steps, keep_state=False, borrow=False):
+        """Queue a request.  borrow=True lends W to the server instead of
+        copying it (the array is held here until its completion is polled;
+        pinned host memory makes the upload a single DMA)."""
         W = np.ascontiguousarray(W, dtype=np.float64)
         shape = W.shape[1:]
         r = Request()
         r.n[0], r.n[1], r.n[2] = shape[2], shape[1], shape[0]
         r.steps = int(steps)
         r.keep_state = 1 if keep_state else 0
+        r.borrow = 1 if borrow else 0
         rid = ctypes.c_uint64()
         _check(lib().mhd_server_submit(self.h, ctypes.byref(r), W.ctypes.data_as(_D), ctypes.byref(rid)),
                "mhd_server_submit")
         self.shapes[rid.value] = tuple(shape)
+        if borrow:
+            self.held[rid.value] = W
         return rid.value
 
     def progress(self):
@@ -343,6 +351,7 @@ class Server:
         out = []
         for k in range(n.value):
             c = buf[k]
+            self.held.pop(c.id, None)
             out.append(dict(id=c.id, status=c.status, steps=c.steps, t_submit=c.t_submit, t_admit=c.t_admit,
                             t_done=c.t_done, totals=np.array(c.totals[:]), cells=c.cells, bytes=c.bytes))
         return out
@@ -362,8 +371,9 @@ class Server:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().mhd_server_destroy(self.h)
+            lib().mhd_server_destroy(self.h)   # waits for the server's stream
             self.h = None
+        self.held = {}
 
     def __del__(self):
         try:

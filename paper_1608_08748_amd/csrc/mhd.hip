@@ -690,7 +690,7 @@ int sync_and_flags(mhd_box* b)
 }
 
 template <typename T>
-int load_f64(mhd_box* b, const double* host, bool prim)
+int load_f64(mhd_box* b, const double* host, bool prim, bool wait = true)
 {
     size_t N = (size_t)b->g.n;
     double* stage = reinterpret_cast<double*>(b->F[0]);
@@ -728,7 +728,7 @@ int load_f64(mhd_box* b, const double* host, bool prim)
     b->timing = saved;
     int st = launch_status();
     if (st) return st;
-    if (hipStreamSynchronize(b->s) != hipSuccess) return MHD_EDEVICE;
+    if (wait && hipStreamSynchronize(b->s) != hipSuccess) return MHD_EDEVICE;
     return MHD_OK;
 }
 
@@ -825,7 +825,8 @@ struct mhd_server {
     struct Pending {
         uint64_t id;
         mhd_request r;
-        std::vector<double> prim;
+        std::vector<double> prim;       // copied state, or
+        const double* src = nullptr;    // the caller's state, borrowed
         double t_submit;
     };
     struct Active {
@@ -921,8 +922,12 @@ int server_admit(mhd_server* sv)
         }
         mhd_params bp = box_params(sv, q.r.n, sv->pool + off, L.total);
         box_bind(b, &bp, L);
-        int st = sv->p.precision == MHD_FP64 ? load_f64<double>(b, q.prim.data(), true)
-                                             : load_f64<float>(b, q.prim.data(), true);
+        // a copied state is freed below, so its upload completes first; a
+        // borrowed one stays valid until the completion is polled
+        const double* src = q.src ? q.src : q.prim.data();
+        const bool wait = q.src == nullptr;
+        int st = sv->p.precision == MHD_FP64 ? load_f64<double>(b, src, true, wait)
+                                             : load_f64<float>(b, src, true, wait);
         if (st) {
             delete b;
             pool_free(sv, off, L.total);
@@ -1222,10 +1227,14 @@ int mhd_server_submit(mhd_server* sv, const mhd_request* r, const double* prim, 
     if (r->n[0] > SERVER_MAX_NX) return MHD_EINVAL;
     if (align256(layout_of(r->n, sv->p.precision, false, false).total) > sv->pool_bytes) return MHD_ENOMEM;
     mhd_server::Pending q;
+    if (r->borrow != 0 && r->borrow != 1) return MHD_EINVAL;
     q.id = sv->next_id++;
     q.r = *r;
     size_t n = (size_t)r->n[0] * r->n[1] * r->n[2];
-    q.prim.assign(prim, prim + (size_t)MHD_NPRIM * n);
+    if (r->borrow)
+        q.src = prim;
+    else
+        q.prim.assign(prim, prim + (size_t)MHD_NPRIM * n);
     q.t_submit = now_s() - sv->t0;
     sv->pending.push_back(std::move(q));
     *id = sv->pending.back().id;

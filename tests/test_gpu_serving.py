@@ -81,3 +81,44 @@ def test_poisson_arrivals_complete():
     assert out["statuses"] == [0]
     assert out["max_active"] <= 3
     assert out["latency_p99"] >= out["latency_p50"] > 0
+
+
+@pytest.mark.parametrize("pinned", [False, True])
+def test_borrowed_states_equal_copied(pinned):
+    # lending the request states (pageable or pinned host memory) instead of
+    # copying them at submission gives the same bits; the binding holds each
+    # lent array until its completion has been polled
+    import torch
+    states = _states()
+    if pinned:
+        lent = []
+        for W in states:
+            P = torch.empty(W.shape, dtype=torch.float64, pin_memory=True).numpy()
+            P[...] = W
+            lent.append(P)
+    else:
+        lent = [W.copy() for W in states]
+    ref, ref_res = _serve(states, binding.FP32_MIXED)
+    sv = binding.Server(1 << 30, max_slots=2, precision=binding.FP32_MIXED)
+    out = serving.run(sv, lent, 3, keep_state=True, borrow=True)
+    assert not sv.held
+    res = [sv.result(r["id"]) for r in out["records"]]
+    sv.close()
+    assert out["statuses"] == [0]
+    for a, b in zip(ref_res, res):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_bad_borrow_flag_rejected():
+    sv = binding.Server(1 << 28, max_slots=2, precision=binding.FP32_MIXED)
+    W = _states()[0]
+    r = binding.Request()
+    r.n[0], r.n[1], r.n[2] = W.shape[3], W.shape[2], W.shape[1]
+    r.steps, r.keep_state, r.borrow = 1, 0, 2
+    import ctypes
+    rid = ctypes.c_uint64()
+    W = np.ascontiguousarray(W)
+    st = binding.lib().mhd_server_submit(sv.h, ctypes.byref(r), W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         ctypes.byref(rid))
+    sv.close()
+    assert st == binding.MHD_EINVAL
