@@ -260,8 +260,9 @@ size_t mhd_server_reserved_bytes(void);
 /* Pool bytes one box of n cells takes (0 for invalid input). */
 size_t mhd_server_box_bytes(const mhd_server_params *p, const int32_t n[3]);
 
-/* Create a server on the caller's workspace and stream (pins a 32 MiB host
- * staging buffer for the launch tables). */
+/* Create a server on the caller's workspace and stream (pins a 64 MiB host
+ * staging buffer for the launch tables of two consecutive rounds and the
+ * finished boxes' totals). */
 int mhd_server_create(const mhd_server_params *p, mhd_server **out);
 
 /* Queue a request with its primitive initial state (host FP64, the
@@ -270,10 +271,16 @@ int mhd_server_create(const mhd_server_params *p, mhd_server **out);
  * not touch the device. */
 int mhd_server_submit(mhd_server *s, const mhd_request *r, const double *prim, uint64_t *id);
 
-/* Admit queued requests while a slot and pool memory are free (first come,
- * first served), run one merged step of every box in flight, wait for it, and
- * retire the boxes that finished their steps (their memory is freed at once).
- * Synchronises.  Outputs the numbers of boxes in flight and still queued. */
+/* One round: admit queued requests while a slot and pool memory are free
+ * (first come, first served), launch one merged step of every box in flight,
+ * then wait for the round launched by the previous call and report the boxes
+ * that finished in it (mhd_server_poll).  Rounds are pipelined: the host work
+ * of a call overlaps the previous round on the device, and a box's completion
+ * is reported by the call after the one that launched its last step (keep
+ * calling while requests are outstanding).  A finished box's memory returns to
+ * the pool when its last step is launched (with keep_state, once its state is
+ * copied out).  Outputs the numbers of boxes still stepping and of queued
+ * requests. */
 int mhd_server_progress(mhd_server *s, int *n_active, int *n_pending);
 
 /* Take up to cap completion records (oldest first). */

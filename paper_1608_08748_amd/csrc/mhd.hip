@@ -843,12 +843,29 @@ struct mhd_server {
     uint64_t next_id;
     double t0;
     std::vector<MultiRec> recs;
+    // pipelined rounds: a call launches its round and then waits for the one
+    // before; the boxes that finished in the last launched round have their
+    // totals and flags on the way to pinned slots (slot k of the round's half)
+    struct Retiring {
+        Active a;
+        int slot;
+    };
+    std::vector<Retiring> retiring;
+    hipEvent_t ev[2];
+    int ev_ready;
+    int64_t rounds;        // rounds launched
+    bool prev_launched;    // the previous call launched a round (event ev[(rounds - 1) & 1])
 };
 
 namespace {
 
-constexpr size_t SERVER_TAB_BYTES = (size_t)32 << 20;
+constexpr size_t SERVER_TAB_BYTES = (size_t)32 << 20;   // launch tables of one round
 constexpr int SERVER_MAX_SLOTS = 1024;
+// pinned return slot of a finished box: NF totals and the fault flags
+constexpr size_t SERVER_RET_BYTES = (NF + 1) * sizeof(double);
+// pinned host area: two table halves (consecutive rounds alternate) and two
+// sets of return slots
+constexpr size_t SERVER_HOST_BYTES = 2 * SERVER_TAB_BYTES + 2 * SERVER_MAX_SLOTS * SERVER_RET_BYTES;
 constexpr int SERVER_MAX_NX = 256;
 
 bool pool_alloc(mhd_server* sv, size_t bytes, size_t* off)
@@ -951,7 +968,7 @@ int server_admit(mhd_server* sv)
 
 // one step of every active box, merged into one launch per program position
 template <typename T>
-int server_step(mhd_server* sv)
+int server_step(mhd_server* sv, int half)
 {
     sv->recs.clear();
     MultiEmit e{ &sv->recs, 0, true, false };
@@ -963,7 +980,7 @@ int server_step(mhd_server* sv)
         emit_step<T>(b, e, a);
         if (e.mismatch || e.k != sv->recs.size()) return MHD_EINVAL;
     }
-    // pack the tables and upload them once
+    // pack the tables into this round's half and upload them once
     size_t off = 0;
     for (MultiRec& r : sv->recs) {
         off = align256(off);
@@ -974,28 +991,75 @@ int server_step(mhd_server* sv)
         off += r.bstart.size() * sizeof(int);
     }
     if (off > SERVER_TAB_BYTES) return MHD_ENOMEM;
+    char* h = sv->htab + (size_t)half * SERVER_TAB_BYTES;
+    char* d = sv->dtab + (size_t)half * SERVER_TAB_BYTES;
     for (MultiRec& r : sv->recs) {
-        memcpy(sv->htab + r.off_args, r.args.data(), r.args.size());
-        memcpy(sv->htab + r.off_bstart, r.bstart.data(), r.bstart.size() * sizeof(int));
+        memcpy(h + r.off_args, r.args.data(), r.args.size());
+        memcpy(h + r.off_bstart, r.bstart.data(), r.bstart.size() * sizeof(int));
     }
-    if (hipMemcpyAsync(sv->dtab, sv->htab, off, hipMemcpyHostToDevice, sv->s) != hipSuccess) return MHD_EDEVICE;
+    if (hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, sv->s) != hipSuccess) return MHD_EDEVICE;
     int nbox = (int)sv->active.size();
     for (MultiRec& r : sv->recs) {
         if (r.total == 0) continue;
-        r.go(sv->dtab + r.off_args, reinterpret_cast<const int*>(sv->dtab + r.off_bstart), nbox, r.total, r.shm,
-             sv->s);
+        r.go(d + r.off_args, reinterpret_cast<const int*>(d + r.off_bstart), nbox, r.total, r.shm, sv->s);
     }
     return launch_status();
+}
+
+double* ret_slot(mhd_server* sv, int half, int k)
+{
+    return reinterpret_cast<double*>(sv->htab + 2 * SERVER_TAB_BYTES +
+                                     ((size_t)half * SERVER_MAX_SLOTS + k) * SERVER_RET_BYTES);
+}
+
+// completion record of a box whose last round has finished (its totals and
+// flags are in its return slot)
+int server_retire(mhd_server* sv, mhd_server::Retiring& r, int half)
+{
+    mhd_server::Active& a = r.a;
+    const double* slot = ret_slot(sv, half, r.slot);
+    uint32_t fl;
+    memcpy(&fl, slot + NF, sizeof(fl));
+    mhd_completion c;
+    memset(&c, 0, sizeof(c));
+    c.id = a.id;
+    c.steps = a.done;
+    c.t_submit = a.t_submit;
+    c.t_admit = a.t_admit;
+    c.cells = (int64_t)a.box->g.n;
+    c.bytes = a.bytes;
+    memcpy(c.totals, slot, NF * sizeof(double));
+    int s2 = (fl & 1u) ? MHD_ENONPHYS : (fl & 2u) ? MHD_ECFL : MHD_OK;
+    c.status = s2;
+    if (a.keep) {
+        // the kept state is copied out before the box's memory is released
+        std::vector<double> buf((size_t)NF * a.box->g.n);
+        int s3 = sv->p.precision == MHD_FP64 ? get_f64<double>(a.box, buf.data())
+                                             : get_f64<float>(a.box, buf.data());
+        if (s3 == MHD_OK || s3 == s2) sv->results[a.id].swap(buf);
+        else if (s3 == MHD_EDEVICE) return s3;
+        pool_free(sv, a.off, a.bytes);
+    }
+    c.t_done = now_s() - sv->t0;
+    sv->done.push_back(c);
+    delete a.box;
+    return MHD_OK;
 }
 
 int server_progress(mhd_server* sv, int* nact, int* npend)
 {
     int st = server_admit(sv);
     if (st) return st;
+    std::vector<mhd_server::Retiring> now_ret;
+    const int half = (int)(sv->rounds & 1);
+    bool launched = false;
     if (!sv->active.empty()) {
-        st = sv->p.precision == MHD_FP64 ? server_step<double>(sv) : server_step<float>(sv);
+        st = sv->p.precision == MHD_FP64 ? server_step<double>(sv, half) : server_step<float>(sv, half);
         if (st) return st;
-        if (hipStreamSynchronize(sv->s) != hipSuccess) return MHD_EDEVICE;
+        // boxes that have run their steps leave the round: their totals and
+        // flags go to pinned slots behind the round on the stream, and (unless
+        // their state is kept) their memory returns to the pool at once, since
+        // anything that reuses it is queued behind
         std::vector<mhd_server::Active> keep;
         for (mhd_server::Active& a : sv->active) {
             a.done++;
@@ -1003,29 +1067,33 @@ int server_progress(mhd_server* sv, int* nact, int* npend)
                 keep.push_back(a);
                 continue;
             }
-            mhd_completion c;
-            memset(&c, 0, sizeof(c));
-            c.id = a.id;
-            c.steps = a.done;
-            c.t_submit = a.t_submit;
-            c.t_admit = a.t_admit;
-            c.cells = (int64_t)a.box->g.n;
-            c.bytes = a.bytes;
-            int s2 = sv->p.precision == MHD_FP64 ? totals<double>(a.box, c.totals) : totals<float>(a.box, c.totals);
-            c.status = s2;
-            if (a.keep && (s2 == MHD_OK || s2 == MHD_ENONPHYS || s2 == MHD_ECFL)) {
-                std::vector<double> buf((size_t)NF * a.box->g.n);
-                int s3 = sv->p.precision == MHD_FP64 ? get_f64<double>(a.box, buf.data())
-                                                     : get_f64<float>(a.box, buf.data());
-                if (s3 == MHD_OK || s3 == s2) sv->results[a.id].swap(buf);
-            }
-            c.t_done = now_s() - sv->t0;
-            sv->done.push_back(c);
-            pool_free(sv, a.off, a.bytes);
-            delete a.box;
+            const int k = (int)now_ret.size();
+            double* slot = ret_slot(sv, half, k);
+            int s2 = sv->p.precision == MHD_FP64 ? totals_launch<double>(a.box) : totals_launch<float>(a.box);
+            if (s2 ||
+                hipMemcpyAsync(slot, a.box->tot_dev, NF * sizeof(double), hipMemcpyDeviceToHost, sv->s) != hipSuccess ||
+                hipMemcpyAsync(slot + NF, a.box->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, sv->s) != hipSuccess)
+                return MHD_EDEVICE;
+            now_ret.push_back({ a, k });
+            if (!a.keep) pool_free(sv, a.off, a.bytes);
         }
         sv->active.swap(keep);
+        if (hipEventRecord(sv->ev[half], sv->s) != hipSuccess) return MHD_EDEVICE;
+        sv->rounds++;
+        launched = true;
     }
+    // the previous round: wait for it and report the boxes that finished in it
+    if (sv->prev_launched) {
+        const int ph = half ^ 1;   // round rounds - 1 (launched by the previous call)
+        if (hipEventSynchronize(sv->ev[ph]) != hipSuccess) return MHD_EDEVICE;
+        for (mhd_server::Retiring& r : sv->retiring) {
+            st = server_retire(sv, r, ph);
+            if (st) return st;
+        }
+        sv->retiring.clear();
+    }
+    sv->retiring.swap(now_ret);
+    sv->prev_launched = launched;
     if (nact) *nact = (int)sv->active.size();
     if (npend) *npend = (int)sv->pending.size();
     return MHD_OK;
@@ -1180,7 +1248,7 @@ const char* mhd_strerror(int status)
     }
 }
 
-size_t mhd_server_reserved_bytes(void) { return SERVER_TAB_BYTES; }
+size_t mhd_server_reserved_bytes(void) { return 2 * SERVER_TAB_BYTES; }
 
 size_t mhd_server_box_bytes(const mhd_server_params* p, const int32_t n[3])
 {
@@ -1198,24 +1266,34 @@ int mhd_server_create(const mhd_server_params* p, mhd_server** out)
                        p->T_unit_K, p->t_unit_s))
         return MHD_EINVAL;
     if (p->max_slots < 1 || p->max_slots > SERVER_MAX_SLOTS) return MHD_EINVAL;
-    if (!p->workspace || p->workspace_bytes < SERVER_TAB_BYTES + 4096) return MHD_ENOMEM;
+    if (!p->workspace || p->workspace_bytes < 2 * SERVER_TAB_BYTES + 4096) return MHD_ENOMEM;
     if (((uintptr_t)p->workspace) & 255) return MHD_EINVAL;
     mhd_server* sv = new (std::nothrow) mhd_server;
     if (!sv) return MHD_ENOMEM;
     sv->p = *p;
     sv->s = reinterpret_cast<hipStream_t>(p->stream);
     sv->dtab = reinterpret_cast<char*>(p->workspace);
-    sv->pool = sv->dtab + SERVER_TAB_BYTES;
-    sv->pool_bytes = (p->workspace_bytes - SERVER_TAB_BYTES) & ~(size_t)255;
+    sv->pool = sv->dtab + 2 * SERVER_TAB_BYTES;
+    sv->pool_bytes = (p->workspace_bytes - 2 * SERVER_TAB_BYTES) & ~(size_t)255;
     sv->freel.push_back(std::make_pair((size_t)0, sv->pool_bytes));
     sv->used = sv->peak = 0;
     sv->next_id = 1;
     sv->t0 = now_s();
     sv->htab = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void**>(&sv->htab), SERVER_TAB_BYTES, hipHostMallocDefault) != hipSuccess) {
+    sv->rounds = 0;
+    sv->prev_launched = false;
+    sv->ev_ready = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&sv->htab), SERVER_HOST_BYTES, hipHostMallocDefault) != hipSuccess) {
         delete sv;
         return MHD_EDEVICE;
     }
+    if (hipEventCreateWithFlags(&sv->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sv->ev[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(sv->htab);
+        delete sv;
+        return MHD_EDEVICE;
+    }
+    sv->ev_ready = 1;
     *out = sv;
     return MHD_OK;
 }
@@ -1284,6 +1362,11 @@ int mhd_server_destroy(mhd_server* sv)
     if (!sv) return MHD_OK;
     (void)hipStreamSynchronize(sv->s);
     for (mhd_server::Active& a : sv->active) delete a.box;
+    for (mhd_server::Retiring& r : sv->retiring) delete r.a.box;
+    if (sv->ev_ready) {
+        (void)hipEventDestroy(sv->ev[0]);
+        (void)hipEventDestroy(sv->ev[1]);
+    }
     if (sv->htab) (void)hipHostFree(sv->htab);
     delete sv;
     return MHD_OK;

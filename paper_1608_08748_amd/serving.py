@@ -1,7 +1,7 @@
 """Serving driver: requests arrive (Poisson process or all at once), are
 submitted to a ``binding.Server`` as they arrive, and the host loop calls
-``progress`` (admission + one merged step of every box in flight) until all
-requests have completed.  Latency is arrival to completion on the host clock;
+``progress`` (admission + one merged step of every box in flight, pipelined
+one round deep) until all requests have completed.  Latency is arrival to completion on the host clock;
 throughput is total cell-updates over the span from the first arrival to the
 last completion."""
 import time
@@ -41,7 +41,9 @@ def run(server, states, steps, arrivals=None, keep_state=False, borrow=False):
             c["t_complete"] = t_poll
             c["latency"] = t_poll - float(arr[i])
             rec[i] = c
-        if na == 0 and npend == 0 and nxt < nreq:
+        # idle until the next arrival only once every submitted request has
+        # been reported (the last round's completions come with the next call)
+        if na == 0 and npend == 0 and nxt < nreq and len(rec) == nxt:
             wait = arr[order[nxt]] - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
