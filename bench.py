@@ -146,6 +146,22 @@ def _roofline(timing, ncell, esz, workload):
     return out
 
 
+# minimum HBM traffic of a whole step: each of the six Runge-Kutta substages
+# reads its inputs and the stage-start state once and writes its outputs once,
+# and the tail reads the face fields: 126 field passes per cell-update
+STEP_FIELD_PASSES = 126
+
+
+def _step_roofline(cell_updates_per_s, esz):
+    """The whole step's throughput as a fraction of the HBM roofline, against
+    the minimum traffic per cell-update (126 field passes of esz bytes)."""
+    per_cell = STEP_FIELD_PASSES * esz
+    gbs = cell_updates_per_s * per_cell / 1e9
+    return {"alg_bytes_per_cell_update": per_cell, "achieved_gbs": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "roofline_cell_updates_per_s": round(HBM_PEAK_GBS * 1e9 / per_cell, 1)}
+
+
 def _cpu_baseline(n=192, steps=3, cooling=False, grav_G=0.0, ionisation=False):
     import oracle
     from paper_1608_08748_amd import inputs
@@ -220,6 +236,7 @@ def _serving_bench(args):
                                "Poisson arrivals at 0.8 x saturated capacity" % (len(states), steps),
                    "hbm_budget_bytes": budget, "max_slots": slots, "request_states": "pinned host memory, lent",
                    "parallelism": "single GPU, merged multi-box launches"},
+        "step_roofline": _step_roofline(poi["throughput"], 4),
         "latency_p50_s": round(poi["latency_p50"], 4), "latency_p99_s": round(poi["latency_p99"], 4),
         "arrival_rate_per_s": round(req_rate, 3),
         "poisson": {k: poi[k] for k in ("throughput", "span_s", "rounds", "max_active", "statuses", "latency_mean",
@@ -294,6 +311,7 @@ def _largest_box_bench(args):
                    "cells": ncell, "grid": [n, n, n], "workspace_bytes": int(box.ws.numel()),
                    "parallelism": "single GPU"},
         "roofline": _roofline(timing, ncell, 4, "c4"),
+        "step_roofline": _step_roofline(ncell * steps / el, 4),
         "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
         "conservation_drift": drift,
     }
@@ -386,6 +404,7 @@ def main():
                    "gamma": 5.0 / 3.0, "theta": 1.0, "heating_cooling": cool, "self_gravity": gG > 0, "ionisation": ion,
                    "parallelism": "single GPU"},
         "roofline": _roofline(timing, ncell, esz, args.config),
+        "step_roofline": _step_roofline(ncell * steps / el, esz),
         "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
     }
     tot = box.totals()
