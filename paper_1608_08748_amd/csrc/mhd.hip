@@ -434,11 +434,11 @@ void emit_nonadv_substage_t(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout
         fa.rpb = rpb;
         int blocks = (g.ny * g.nz + rpb - 1) / rpb;
         if (g.nx <= 256)
-            e.template launch<BFaceXRows<T, 256, ION>>(MHD_K_NONADV_FACE, blocks, 256 * 18 * sizeof(T), fa);
+            e.template launch<BFaceXRows<T, 256, ION>>(MHD_K_NONADV_FACE, blocks, 256 * XROW_SLOTS * sizeof(T), fa);
         else if (g.nx <= 512)
-            e.template launch<BFaceXRows<T, 512, ION>>(MHD_K_NONADV_FACE, blocks, 512 * 18 * sizeof(T), fa);
+            e.template launch<BFaceXRows<T, 512, ION>>(MHD_K_NONADV_FACE, blocks, 512 * XROW_SLOTS * sizeof(T), fa);
         else if constexpr (sizeof(T) == 4)   // 1024-thread rows only in FP32 (register budget)
-            e.template launch<BFaceXRows<T, 1024, ION>>(MHD_K_NONADV_FACE, blocks, 1024 * 18 * sizeof(T), fa);
+            e.template launch<BFaceXRows<T, 1024, ION>>(MHD_K_NONADV_FACE, blocks, 1024 * XROW_SLOTS * sizeof(T), fa);
     } else {
         fa.rpb = 0;
         e.template launch<BFacePair<T, 0, ION>>(MHD_K_NONADV_FACE, b->nblocks, 0, fa);

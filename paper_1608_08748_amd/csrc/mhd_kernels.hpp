@@ -253,8 +253,11 @@ struct BFacePair {
 // kernels that ran before), the p dV work, the gravity sources and the
 // Runge-Kutta combination of m, E, e (Sec. 2.2).  Only the edge-field
 // components of the x faces are stored, for the face-field update.  Dynamic
-// LDS: 18 x NT values, value k of thread t at k * NT + t, reused by the five
-// exchanges.
+// LDS: XROW_SLOTS x NT values, value k of thread t at k * NT + t: primitives
+// in slots 0-7, slopes 8-13, interface values 0-5, parabola sides 6-23 and
+// x-face fluxes 0-4, so each exchange needs one barrier.
+constexpr int XROW_SLOTS = 24;
+
 template <typename T, int MAXT, bool ION>
 struct BFaceXRows {
     static constexpr int NT = MAXT;
@@ -328,44 +331,38 @@ struct BFaceXRows {
             }
         }
         __syncthreads();
-        // parabolas of the own cell; the upper interface value is the right
-        // cell's lower one
+        // parabolas of the own cell (the upper interface value is the right
+        // cell's lower one); its right side is published in slots 6-23
+        // (primitives and slopes there are no longer read)
         Side<T> R;
-        T pub[18];
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
                 T fr = sm[v * NT + tr];
                 Par<T> P = parabola_finish(q0[v], q1[v], q2[v], q3[v], q4[v], fl[v], fr, dm[v]);
                 side_right(P, R, v);
-                pub[3 * v + 0] = P.qR;
-                pub[3 * v + 1] = P.dq;
-                pub[3 * v + 2] = P.q6;
+                sm[(6 + 3 * v + 0) * NT + tid] = P.qR;
+                sm[(6 + 3 * v + 1) * NT + tid] = P.dq;
+                sm[(6 + 3 * v + 2) * NT + tid] = P.q6;
             }
         }
         __syncthreads();
-        if (act) {
-#pragma unroll
-            for (int q = 0; q < 18; q++) sm[q * NT + tid] = pub[q];
-        }
-        __syncthreads();
+        // the face solve; its fluxes go to slots 0-4 (the interface values
+        // there were read before the barrier)
         T out[7];
         if (act) {
             Side<T> L;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                L.e[v] = sm[(3 * v + 0) * NT + tl];
-                L.dq[v] = sm[(3 * v + 1) * NT + tl];
-                L.q6[v] = sm[(3 * v + 2) * NT + tl];
+                L.e[v] = sm[(6 + 3 * v + 0) * NT + tl];
+                L.dq[v] = sm[(6 + 3 * v + 1) * NT + tl];
+                L.q6[v] = sm[(6 + 3 * v + 2) * NT + tl];
             }
             // parabola variables 3, 4, 5 are Bt1, Bt2, p
             face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
                        T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
             A.F[5 * N + c] = out[5];
             A.F[6 * N + c] = out[6];
-        }
-        __syncthreads();
-        if (act) {
 #pragma unroll
             for (int v = 0; v < 5; v++) sm[v * NT + tid] = out[v];
         }
