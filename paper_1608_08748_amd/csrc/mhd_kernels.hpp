@@ -243,6 +243,13 @@ struct BFacePair {
     }
 };
 
+// The y and z face kernels store, for FP32 state, the per-cell difference of
+// the five fluxes between a cell's upper and lower face (what the update
+// reads) instead of the face values, so the update reads one value per flux;
+// the two edge-field components are stored per face either way.  (For FP64
+// the carried fluxes would not fit the marching kernel's registers.)
+template <typename T> struct FluxDiff { static constexpr bool v = sizeof(T) == 4; };
+
 // NONADV faces along x with whole x rows per block, fused with the update of
 // m, E and e.  Each thread owns one cell, forms its primitives and computes,
 // once each, its limited slopes, the interface values at its lower face and
@@ -378,8 +385,13 @@ struct BFaceXRows {
 #pragma unroll
         for (int v = 0; v < 5; v++) {
             dF[0][v] = sm[v * NT + tr] - out[v];
-            dF[1][v] = Fy[v * N + c + dyp] - Fy[v * N + c];
-            dF[2][v] = Fz[v * N + c + dzp] - Fz[v * N + c];
+            if (FluxDiff<T>::v) {   // the marches stored per-cell differences
+                dF[1][v] = Fy[v * N + c];
+                dF[2][v] = Fz[v * N + c];
+            } else {
+                dF[1][v] = Fy[v * N + c + dyp] - Fy[v * N + c];
+                dF[2][v] = Fz[v * N + c + dzp] - Fz[v * N + c];
+            }
         }
         T inc[5];
         // momentum component a takes slot (a - d) mod 3 from direction d
@@ -437,7 +449,8 @@ struct BFaceXRows {
 // a segment of `seg` faces with a sliding 5-cell window of primitives in
 // registers, so each cell's primitives and parabolas are formed once per
 // segment (seg + 1 per seg faces); threads are consecutive in x, so every load
-// is coalesced.
+// is coalesced.  With per-cell differences the thread also solves the upper
+// face of its segment's last cell; the previous face's fluxes wait in LDS.
 template <typename T, int D, bool ION>
 struct BFaceMarch {
     static constexpr int NT = NTH;
@@ -511,8 +524,11 @@ struct BFaceMarch {
             int cn = base + wrapc(x + 2, nd) * stride;
             raw_load<T, D, ION>(A.U, cn, cn + o1, cn + o2, nr);
         };
+        constexpr bool DIFF = FluxDiff<T>::v;
+        const int xe = DIFF ? x1 + 1 : x1;   // faces solved: x0 .. xe - 1
+        __shared__ T prev[DIFF ? 5 : 1][NT];
         fetch(x0);
-        for (int x = x0; x < x1; x++) {
+        for (int x = x0; x < xe; x++) {
             T qn[6], gn;
             raw_prim<T, ION>(nr, A.a.gamma, qn, gn);
 #pragma unroll
@@ -526,7 +542,7 @@ struct BFaceMarch {
                 for (int m = 0; m < 4; m++) gw[m] = gw[m + 1];
                 gw[4] = gn;
             }
-            if (x + 1 < x1) fetch(x + 1);
+            if (x + 1 < xe) fetch(x + 1);
             Side<T> R, Ln;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
@@ -539,12 +555,28 @@ struct BFaceMarch {
                 dmc[v] = dn;
                 fl[v] = fr;
             }
-            int c = base + x * stride;
+            // face x is the lower face of cell x (with differences, x = x1 is
+            // the upper face of the last cell, periodic)
+            int c = base + (DIFF ? wrapc(x, nd) : x) * stride;
             T out[7];
             // left cell x-1 is window slot 1, right cell x is slot 2
             face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], A.U.f[BX + D][c], L,
                        R, gm, ION ? gw[1] : gm, ION ? gw[2] : gm, ION, ydx, out);
-            store_face(A.F, N, c, out);
+            if (!DIFF) {
+                store_face(A.F, N, c, out);
+            } else {
+                if (x < x1) {
+                    A.F[5 * N + c] = out[5];
+                    A.F[6 * N + c] = out[6];
+                }
+                if (x > x0) {
+                    const int cm = base + (x - 1) * stride;
+#pragma unroll
+                    for (int v = 0; v < 5; v++) A.F[v * N + cm] = out[v] - prev[v][tid];
+                }
+#pragma unroll
+                for (int v = 0; v < 5; v++) prev[v][tid] = out[v];
+            }
             L = Ln;
         }
     }
@@ -620,7 +652,7 @@ struct BNonadvUpdate {
         {
             int c = i + nx * j + nxy * k0;
             int zm = c + ((k0 == 0 ? nz - 1 : k0 - 1) - k0) * nxy;
-            if (FULL) {
+            if (FULL && !FluxDiff<T>::v) {
 #pragma unroll
                 for (int v = 0; v < 5; v++) fzc[v] = Fz[v * N + c];
             }
@@ -645,9 +677,14 @@ struct BNonadvUpdate {
 #pragma unroll
                 for (int v = 0; v < 5; v++) {
                     dF[0][v] = Fx[v * N + xp] - Fx[v * N + c];
-                    dF[1][v] = Fy[v * N + yp] - Fy[v * N + c];
-                    fzp[v] = Fz[v * N + zp];
-                    dF[2][v] = fzp[v] - fzc[v];
+                    if (FluxDiff<T>::v) {   // the marches stored per-cell differences
+                        dF[1][v] = Fy[v * N + c];
+                        dF[2][v] = Fz[v * N + c];
+                    } else {
+                        dF[1][v] = Fy[v * N + yp] - Fy[v * N + c];
+                        fzp[v] = Fz[v * N + zp];
+                        dF[2][v] = fzp[v] - fzc[v];
+                    }
                 }
                 // momentum component a takes slot (a - d) mod 3 from direction d
                 inc[MX] = -dtdx * ((dF[0][0] + dF[1][2]) + dF[2][1]);
@@ -677,8 +714,10 @@ struct BNonadvUpdate {
                     }
                     inc[EN] -= dt * work;
                 }
+                if (!FluxDiff<T>::v) {
 #pragma unroll
-                for (int v = 0; v < 5; v++) fzc[v] = fzp[v];
+                    for (int v = 0; v < 5; v++) fzc[v] = fzp[v];
+                }
             }
 
             // edge fields on the upper edges (Ex, Ey at z+1/2; Ex at y+1/2, Ey
@@ -1098,8 +1137,13 @@ struct BAdvZUpdate {
             }
             vr[0] = vr[1];
             vm[0] = vm[1];
-            vr[1] = own_v ? w[0][3] : nvr;
-            vm[1] = own_v ? w[3][3] : nvm;
+            if constexpr (own_v) {
+                vr[1] = w[0][3];
+                vm[1] = w[3][3];
+            } else {
+                vr[1] = nvr;
+                vm[1] = nvm;
+            }
             if (x + 1 < x1) fetch(x + 1);
             // the cell's x/y flux differences and Runge-Kutta input, loaded
             // before the z flux is formed so the loads overlap it, and before
