@@ -585,9 +585,10 @@ struct BFaceMarch {
 // NONADV update: flux differences, p dV work, face-field update from edge
 // fields (Sec. 2.5), Runge-Kutta combination (Sec. 2.2).  dbg != 0 writes
 // tau R(U) instead of the combination.  Each thread marches along z over a
-// segment of cells (ZTile); the z-face values at the upper face of cell k and
-// the two edge fields on its upper z edges are the lower ones of cell k+1, so
-// they are carried instead of read or formed again (same arithmetic).
+// segment of cells (ZTile); the Ex, Ey on the upper z edges of cell k, the
+// edge-field components they read, and (full update, FP64) the z-face fluxes
+// at its upper face are the lower ones of cell k+1, so they are carried
+// instead of read or formed again (same arithmetic).
 template <typename T>
 struct NonadvUpdateArgs {
     Geo g;
