@@ -122,3 +122,35 @@ def test_bad_borrow_flag_rejected():
                                          ctypes.byref(rid))
     sv.close()
     assert st == binding.MHD_EINVAL
+
+
+def test_close_with_rounds_in_flight():
+    # a server closed while boxes are still stepping and others have just
+    # finished (their completion not yet reported) releases everything; a new
+    # server on the same device then serves the same request bit for bit
+    states = _states()
+    sv = binding.Server(1 << 30, max_slots=3, precision=binding.FP32_MIXED)
+    for k, W in enumerate(states):
+        sv.submit(W, 2 + 3 * k, keep_state=True, borrow=bool(k % 2))
+    for _ in range(3):
+        sv.progress()
+    sv.close()
+    assert not sv.held
+    ref, ref_res = _serve(states[:1], binding.FP32_MIXED)
+    again, again_res = _serve(states[:1], binding.FP32_MIXED)
+    np.testing.assert_array_equal(ref_res[0], again_res[0])
+
+
+def test_progress_reports_each_request_once():
+    # pipelined rounds: every request is reported exactly once, after its
+    # last step, and progress keeps returning once the queue is empty
+    states = _states()
+    sv = binding.Server(1 << 30, max_slots=2, precision=binding.FP64)
+    ids = [sv.submit(W, 2) for W in states]
+    seen = []
+    for _ in range(20):
+        na, npend = sv.progress()
+        seen += [c["id"] for c in sv.poll()]
+    sv.close()
+    assert sorted(seen) == sorted(ids)
+    assert (na, npend) == (0, 0)
