@@ -139,9 +139,10 @@ __device__ __forceinline__ void raw_load(const CFields<T>& U, int c, int c1, int
 template <typename T, bool ION>
 __device__ __forceinline__ void raw_prim(const Raw<T>& r, double gamma, T q[6], T& gam)
 {
-    q[0] = r.mn / r.rho;
-    q[1] = r.m1 / r.rho;
-    q[2] = r.m2 / r.rho;
+    const T ir = rcp_nr(r.rho);   // one reciprocal for the three velocities
+    q[0] = r.mn * ir;
+    q[1] = r.m1 * ir;
+    q[2] = r.m2 * ir;
     q[3] = T(0.5) * (r.b1 + r.b1p);
     q[4] = T(0.5) * (r.b2 + r.b2p);
     if (ION) {
@@ -238,7 +239,8 @@ struct BFacePair {
         T out[7];
         const T gm = T(A.a.gamma);
         face_solve(rho[2], q[5][2], q[3][2], q[4][2], rho[3], q[5][3], q[3][3], q[4][3], A.U.f[BX + D][c], L, R,
-                   gm, gam[2], gam[3], ION, T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+                   gm, gam[2], gam[3], ION, T(A.a.theta * (step_dt(A.a) / A.a.h)), root_nr(rho[2]), root_nr(rho[3]),
+                   out);
         store_face(A.F, N, c, out);
     }
 };
@@ -261,8 +263,9 @@ template <typename T> struct FluxDiff { static constexpr bool v = sizeof(T) == 4
 // Runge-Kutta combination of m, E, e (Sec. 2.2).  Only the edge-field
 // components of the x faces are stored, for the face-field update.  Dynamic
 // LDS: XROW_SLOTS x NT values, value k of thread t at k * NT + t: primitives
-// in slots 0-7, slopes 8-13, interface values 0-5, parabola sides 6-23 and
-// x-face fluxes 0-4, so each exchange needs one barrier.
+// in slots 0-7 with sqrt(rho) in 14, slopes 8-13, interface values 0-5,
+// parabola sides 6-23 and x-face fluxes 0-4, so each exchange needs one
+// barrier.
 constexpr int XROW_SLOTS = 24;
 
 template <typename T, int MAXT, bool ION>
@@ -295,7 +298,7 @@ struct BFaceXRows {
         const int dzp = ((k + 1 == g.nz ? 0 : k + 1) - k) * g.nxy;
 
         // own cell: conserved values, primitives
-        T q2[6], rho = T(0), gam = gm, bn = T(0);
+        T q2[6], rho = T(0), gam = gm, bn = T(0), srho = T(0);
         if (act) {
             Raw<T> rw;
             raw_load<T, 0, ION>(A.U, c, c + dyp, c + dzp, rw);
@@ -306,12 +309,14 @@ struct BFaceXRows {
             for (int v = 0; v < 6; v++) sm[v * NT + tid] = q2[v];
             sm[6 * NT + tid] = rho;
             if (ION) sm[7 * NT + tid] = gam;
+            srho = root_nr(rho);
+            sm[14 * NT + tid] = srho;
         }
         __syncthreads();
         // the 5-cell line of each variable; the left cell's density (and
         // gamma); slopes of the own cell
         T q0[6], q1[6], q3[6], q4[6], dm[6], fl[6];
-        T rl = T(0), gl = gm;
+        T rl = T(0), gl = gm, srl = T(0);
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
@@ -321,6 +326,7 @@ struct BFaceXRows {
                 q4[v] = sm[v * NT + tp2];
             }
             rl = sm[6 * NT + tl];
+            srl = sm[14 * NT + tl];
             if (ION) gl = sm[7 * NT + tl];
 #pragma unroll
             for (int v = 0; v < 6; v++) {
@@ -367,7 +373,7 @@ struct BFaceXRows {
             }
             // parabola variables 3, 4, 5 are Bt1, Bt2, p
             face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
-                       T(A.a.theta * (step_dt(A.a) / A.a.h)), out);
+                       T(A.a.theta * (step_dt(A.a) / A.a.h)), srl, srho, out);
             A.F[5 * N + c] = out[5];
             A.F[6 * N + c] = out[6];
 #pragma unroll
@@ -527,6 +533,9 @@ struct BFaceMarch {
         constexpr bool DIFF = FluxDiff<T>::v;
         const int xe = DIFF ? x1 + 1 : x1;   // faces solved: x0 .. xe - 1
         __shared__ T prev[DIFF ? 5 : 1][NT];
+        // sqrt(rho) of the face's left cell, carried (window slot 2 before
+        // the first slide is slot 1 of the first face)
+        T srl = root_nr(w[6][2]);
         fetch(x0);
         for (int x = x0; x < xe; x++) {
             T qn[6], gn;
@@ -560,8 +569,10 @@ struct BFaceMarch {
             int c = base + (DIFF ? wrapc(x, nd) : x) * stride;
             T out[7];
             // left cell x-1 is window slot 1, right cell x is slot 2
+            const T srr = root_nr(w[6][2]);
             face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], A.U.f[BX + D][c], L,
-                       R, gm, ION ? gw[1] : gm, ION ? gw[2] : gm, ION, ydx, out);
+                       R, gm, ION ? gw[1] : gm, ION ? gw[2] : gm, ION, ydx, srl, srr, out);
+            srl = srr;
             if (!DIFF) {
                 store_face(A.F, N, c, out);
             } else {

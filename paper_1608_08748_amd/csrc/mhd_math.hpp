@@ -255,13 +255,13 @@ __device__ __forceinline__ void side_right(const Par<T>& P, Side<T>& S, int v)
 template <typename T>
 __device__ __forceinline__ void face_solve(T rl, T pl, T b1l, T b2l, T rr, T pr, T b1r, T b2r, T bn,
                                            const Side<T>& L, const Side<T>& R, T gm, T gml, T gmr, bool ion, T ydx,
-                                           T out[7])
+                                           T sl, T sr, T out[7])
 {
     const T eps = Eps<T>::v;
-    // face averages (sqrt(rho) weights; cross weights for Bt); with the
+    // face averages (sqrt(rho) weights, sl = root_nr(rl) and sr = root_nr(rr)
+    // formed once per cell by the caller; cross weights for Bt); with the
     // ionisation network the adiabatic index is the cells' gamma_eff averaged
     // with the weights of p
-    T sl = root_nr(rl), sr = root_nr(rr);
     T iw = rcp_nr(sl + sr);
     T rho = (sl * rl + sr * rr) * iw;
     T p = (sl * pl + sr * pr) * iw;
