@@ -112,7 +112,7 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 TRAFFIC = {
     # average of the x-row (with the m, E, e update), y-march and z-march
     # face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("95a6153323ff1df4", 3310603079),
+    ("c2", 8, "nonadv_face"): ("323ac34279f38992", 3309651975),
 }
 
 
