@@ -476,6 +476,19 @@ void emit_nonadv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, 
 template <typename T, int D, int NQ, class Emit>
 void emit_adv_face(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a)
 {
+    if constexpr (D == 1) {
+        // y faces: marched along y
+        typename BAdvFaceMarchY<T, NQ>::Args ma;
+        ma.g = b->g;
+        ma.U = cview(in);
+        ma.a = a;
+        ma.F = reinterpret_cast<T*>(b->F[1]);
+        constexpr int SEG = 32;
+        ma.seg = b->g.ny < SEG ? b->g.ny : SEG;
+        long long threads = (long long)b->g.nx * b->g.nz * ((b->g.ny + ma.seg - 1) / ma.seg);
+        e.template launch<BAdvFaceMarchY<T, NQ>>(MHD_K_ADV_FACE, (int)((threads + NTH - 1) / NTH), 0, ma);
+        return;
+    }
     typename BAdvFace<T, D, NQ>::Args fa;
     fa.g = b->g;
     fa.U = cview(in);
@@ -491,8 +504,9 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
-    // one face per thread: an LDS row scheme that computes each cell's
-    // slopes once measured slower here (block barriers, fewer waves)
+    // x faces one per thread (an LDS row scheme that computes each cell's
+    // slopes once measured slower: block barriers, fewer waves); y faces
+    // marched along y, each cell's parabola formed once
     if (b->p.ionisation) {
         emit_adv_face<T, 0, 8>(b, e, in, a);
         emit_adv_face<T, 1, 8>(b, e, in, a);

@@ -1040,6 +1040,122 @@ struct BAdvFace {
     }
 };
 
+// ADV faces along y, marched: each thread walks one y line over a segment of
+// `seg` faces with a sliding 5-cell window of the NQ fields, so each cell's
+// limited slope, lower interface value and parabola are formed once (the
+// per-face kernel forms three slopes, two interface values and a parabola per
+// face); the previous cell's right side and sqrt(rho) are carried.  The face
+// takes the upwind average: the left cell's right part for vf >= 0, the right
+// cell's left part otherwise (same arithmetic as BAdvFace).
+template <typename T, int NQ>
+struct BAdvFaceMarchY {
+    static constexpr int NT = NTH;
+    static constexpr bool XCD = false;
+    struct Args {
+        Geo g;
+        CFields<T> U;
+        T* F;
+        StepArgs a;
+        int seg;
+    };
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
+    {
+        const Geo& g = A.g;
+        const size_t N = (size_t)g.n;
+        const int seg = A.seg;
+        const int nd = g.ny, no = g.nz;
+        const int nseg = (nd + seg - 1) / seg;
+        int t = blk * NT + tid;
+        int i = t % g.nx;
+        int rest = t / g.nx;
+        int o = rest % no;
+        int sgi = rest / no;
+        if (sgi >= nseg) return;
+        const int base = i + g.nxy * o;
+        const int stride = g.nx;
+        const int x0 = sgi * seg;
+        const int x1 = min(x0 + seg, nd);
+        const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
+        const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
+
+        // window: w[q][m] = field q of cell x-2+m (after the slide of face x)
+        T w[NQ][5];
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            int cc = base + wrapc(x0 - 3 + m, nd) * stride;
+#pragma unroll
+            for (int q = 0; q < NQ; q++) w[q][m] = A.U.f[fld[q]][cc];
+        }
+        // parabola of cell x0 - 1 (its right side is read by the first face),
+        // the slope of cell x0 and the interface value at its lower face
+        T pR[NQ], pdq[NQ], p6[NQ], dmc[NQ], fl[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            T d0 = limited_slope(w[q][0], w[q][1], w[q][2]);
+            T d1 = limited_slope(w[q][1], w[q][2], w[q][3]);
+            T d2 = limited_slope(w[q][2], w[q][3], w[q][4]);
+            T f0 = interface_value(w[q][1], w[q][2], d0, d1);
+            T f1 = interface_value(w[q][2], w[q][3], d1, d2);
+            Par<T> P = parabola_finish(w[q][0], w[q][1], w[q][2], w[q][3], w[q][4], f0, f1, d1);
+            pR[q] = P.qR;
+            pdq[q] = P.dq;
+            p6[q] = P.q6;
+            dmc[q] = d2;
+            fl[q] = f1;
+        }
+        // 1 / sqrt(rho) of the face's left cell (window slot 2 before the
+        // first slide is slot 1 of the first face)
+        T rsl = rsqrt_nr(w[0][2]);
+        // the cell entering the window, loaded one face ahead
+        T nw[NQ];
+        auto fetch = [&](int x) {
+            int cn = base + wrapc(x + 2, nd) * stride;
+#pragma unroll
+            for (int q = 0; q < NQ; q++) nw[q] = A.U.f[fld[q]][cn];
+        };
+        fetch(x0);
+        for (int x = x0; x < x1; x++) {
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+#pragma unroll
+                for (int m = 0; m < 4; m++) w[q][m] = w[q][m + 1];
+                w[q][4] = nw[q];
+            }
+            if (x + 1 < x1) fetch(x + 1);
+            // sqrt(rho)-weighted face velocity from cells x-1 (slot 1) and x
+            // (slot 2); sqrt(rho) v = m / sqrt(rho), m_y is field 2
+            const T rsr = rsqrt_nr(w[0][2]);
+            const T vf = (w[2][1] * rsl + w[2][2] * rsr) * rcp_nr(w[0][1] * rsl + w[0][2] * rsr);
+            const bool upw = vf >= T(0);
+            const T y = upw ? ydx * vf : ydx * (-vf);
+            const int c = base + x * stride;
+            T flux[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                // the parabola of cell x (window slots 0..4 = cells x-2..x+2)
+                T dn = limited_slope(w[q][2], w[q][3], w[q][4]);
+                T fr = interface_value(w[q][2], w[q][3], dmc[q], dn);
+                Par<T> P = parabola_finish(w[q][0], w[q][1], w[q][2], w[q][3], w[q][4], fl[q], fr, dmc[q]);
+                Par<T> Pl;
+                Pl.qR = pR[q];
+                Pl.dq = pdq[q];
+                Pl.q6 = p6[q];
+                Pl.qL = T(0);
+                T qup = upw ? avg_right(Pl, y) : avg_left(P, y);
+                flux[q] = vf * qup;
+                pR[q] = P.qR;
+                pdq[q] = P.dq;
+                p6[q] = P.q6;
+                dmc[q] = dn;
+                fl[q] = fr;
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; q++) A.F[q * N + c] = flux[q];
+            rsl = rsr;
+        }
+    }
+};
+
 // ADV z faces fused with the ADV update, for the advected fields Q0 ..
 // Q0+NQ-1 of the order rho, mx, my, mz, E, e, h2, hp: each thread marches along z
 // over a segment of cells with a sliding 6-cell window of those fields, so
