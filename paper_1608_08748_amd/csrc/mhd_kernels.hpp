@@ -1183,23 +1183,34 @@ struct BAdvZUpdate {
     static constexpr int NT = NTH;
     static constexpr bool XCD = false;
     using Args = AdvZArgs<T>;
-    // fluxes of the group's fields through the face between window slots 2
-    // and 3 (cells k and k+1 of a window that starts at k-2), face velocity vf
-    static __device__ __forceinline__ void zflux(const T w[NQ][6], T vf, T ydx, T out[NQ])
+    // Along the march each cell's limited slope, lower interface value and
+    // parabola are formed once: for the face between window slots 2 and 3
+    // (cells k, k+1 of a window that starts at k-2) the parabola of cell k
+    // was formed at the face below (pc: its right side), and the thread forms
+    // that of cell k+1 from the carried slope d1 of cell k+1 and interface
+    // value f1 at k+1/2; the face takes the upwind average.
+    static __device__ __forceinline__ void zflux(const T w[NQ][6], T vf, T ydx, T pR[NQ], T pdq[NQ], T p6[NQ],
+                                                 T d1[NQ], T f1[NQ], T out[NQ])
     {
         bool upw = vf >= T(0);
         T y = upw ? ydx * vf : ydx * (-vf);
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
-            // upwind cell: slot 2 (stencil slots 0..4) or slot 3 (slots 1..5)
-            T q0 = upw ? w[q][0] : w[q][1];
-            T q1 = upw ? w[q][1] : w[q][2];
-            T q2 = upw ? w[q][2] : w[q][3];
-            T q3 = upw ? w[q][3] : w[q][4];
-            T q4 = upw ? w[q][4] : w[q][5];
-            Par<T> P = parabola(q0, q1, q2, q3, q4);
-            T qup = upw ? avg_right(P, y) : avg_left(P, y);
+            T d2 = limited_slope(w[q][3], w[q][4], w[q][5]);
+            T f2 = interface_value(w[q][3], w[q][4], d1[q], d2);
+            Par<T> Pn = parabola_finish(w[q][1], w[q][2], w[q][3], w[q][4], w[q][5], f1[q], f2, d1[q]);
+            Par<T> Pc;
+            Pc.qR = pR[q];
+            Pc.dq = pdq[q];
+            Pc.q6 = p6[q];
+            Pc.qL = T(0);
+            T qup = upw ? avg_right(Pc, y) : avg_left(Pn, y);
             out[q] = vf * qup;
+            pR[q] = Pn.qR;
+            pdq[q] = Pn.dq;
+            p6[q] = Pn.q6;
+            d1[q] = d2;
+            f1[q] = f2;
         }
     }
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
@@ -1237,8 +1248,34 @@ struct BAdvZUpdate {
             T rsl = rsqrt_nr(vr[0]), rsr = rsqrt_nr(vr[1]);
             return (vm[0] * rsl + vm[1] * rsr) * rcp_nr(vr[0] * rsl + vr[1] * rsr);
         };
-        T Flo[NQ];
-        zflux(w, velocity(), ydx, Flo);
+        // the first face (slots 2, 3): both adjacent parabolas; then carry the
+        // upper cell's right side, the slope of the cell above it and the
+        // interface value between them
+        T Flo[NQ], pR[NQ], pdq[NQ], p6[NQ], d1[NQ], f1[NQ];
+        {
+            const T vf = velocity();
+            const bool upw = vf >= T(0);
+            const T y = upw ? ydx * vf : ydx * (-vf);
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                T s0 = limited_slope(w[q][0], w[q][1], w[q][2]);
+                T s1 = limited_slope(w[q][1], w[q][2], w[q][3]);
+                T s2 = limited_slope(w[q][2], w[q][3], w[q][4]);
+                T s3 = limited_slope(w[q][3], w[q][4], w[q][5]);
+                T i0 = interface_value(w[q][1], w[q][2], s0, s1);
+                T i1 = interface_value(w[q][2], w[q][3], s1, s2);
+                T i2 = interface_value(w[q][3], w[q][4], s2, s3);
+                Par<T> Pl = parabola_finish(w[q][0], w[q][1], w[q][2], w[q][3], w[q][4], i0, i1, s1);
+                Par<T> Pr = parabola_finish(w[q][1], w[q][2], w[q][3], w[q][4], w[q][5], i1, i2, s2);
+                T qup = upw ? avg_right(Pl, y) : avg_left(Pr, y);
+                Flo[q] = vf * qup;
+                pR[q] = Pr.qR;
+                pdq[q] = Pr.dq;
+                p6[q] = Pr.q6;
+                d1[q] = s3;
+                f1[q] = i2;
+            }
+        }
         // the values cell x needs from beyond the window (cell x+3 entering
         // it; rho and mz of cell x+1 when the group holds neither) are loaded
         // one cell ahead, so the loads are in flight during the previous cell
@@ -1290,7 +1327,7 @@ struct BAdvZUpdate {
             }
             // upper face of cell x: between slots 2 (cell x) and 3 (cell x+1)
             T Fup[NQ];
-            zflux(w, velocity(), ydx, Fup);
+            zflux(w, velocity(), ydx, pR, pdq, p6, d1, f1, Fup);
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 T dz = Fup[q] - Flo[q];
