@@ -125,6 +125,9 @@ bool valid_params(const mhd_params* p)
 // ionisation network
 size_t face_values(bool ion) { return ion ? NFACE + 1 : NFACE; }
 
+ZTile ztile_of(const Geo& g, int nt);
+int ztile_blocks(const Geo& g, const ZTile& z);
+
 Layout layout_of(const int32_t n[3], int precision, bool grav, bool ion)
 {
     Layout L;
@@ -136,7 +139,16 @@ Layout layout_of(const int32_t n[3], int precision, bool grav, bool ion)
     // the face scratch doubles as host staging (MHD_NPRIM or NF FP64 fields)
     size_t stage = align256((size_t)NF * N * 8);
     L.F = 3 * fbytes > stage ? 3 * fbytes : stage;
-    L.part = align256(nb * NF * sizeof(double));
+    // per-block partials: the totals (NF per cell-parallel block) and the
+    // CFL speed maxima of the z-marching update that runs the tail
+    Geo g;
+    g.nx = n[0];
+    g.ny = n[1];
+    g.nz = n[2];
+    g.nxy = n[0] * n[1];
+    g.n = (int)N;
+    size_t zb = (size_t)ztile_blocks(g, ztile_of(g, NTH));
+    L.part = align256((nb * NF > zb ? nb * NF : zb) * sizeof(double));
     L.misc = 3 * 256;
     // self-gravity: the potential and the FFT tables (the complex scratch of
     // the Poisson solve is the x face scratch, free at that point)
@@ -361,7 +373,7 @@ constexpr int ZMARCH_SEG = 32;
 
 // tiles of the z-marching update kernels: 64 x cells (a wave) by nt / 64
 // rows for blocks of nt threads, narrower for thin boxes
-ZTile ztile_of(const Geo& g, int nt = NTH)
+ZTile ztile_of(const Geo& g, int nt)
 {
     ZTile z;
     z.tx = g.nx < 64 ? g.nx : 64;
@@ -498,8 +510,11 @@ void emit_adv_face(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a)
 }
 
 
+// tail: the step's last substage, whose energy-group launch runs the tail of
+// the step and leaves the CFL speed maxima in b->part
 template <typename T, class Emit>
-void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg)
+void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, const StepArgs& a, RK rk, int dbg,
+                       bool tail = false)
 {
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
@@ -525,13 +540,19 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     ua.a = a;
     ua.rk = rk;
     ua.dbg = dbg;
-    ua.zt = ztile_of(b->g);
+    ua.zt = ztile_of(b->g, NTH);
+    ua.ch = chem_args(b);
+    ua.part = b->part;
+    ua.flags = b->flags;
     const int blocks = ztile_blocks(b->g, ua.zt);
     e.template launch<BAdvZUpdate<T, 0, 4>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // rho, m
-    if (b->p.ionisation)
-        e.template launch<BAdvZUpdate<T, 4, 4>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2, hp
-    else
-        e.template launch<BAdvZUpdate<T, 4, 3>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2
+    if (b->p.ionisation) {
+        if (tail) e.template launch<BAdvZUpdate<T, 4, 4, true>>(MHD_K_ADV_UPDATE, blocks, 0, ua);
+        else e.template launch<BAdvZUpdate<T, 4, 4>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2, hp
+    } else {
+        if (tail) e.template launch<BAdvZUpdate<T, 4, 3, true>>(MHD_K_ADV_UPDATE, blocks, 0, ua);
+        else e.template launch<BAdvZUpdate<T, 4, 3>>(MHD_K_ADV_UPDATE, blocks, 0, ua);   // E, e, h2
+    }
 }
 
 // NONADV stage: the M and B groups each rotate through their three slots
@@ -551,8 +572,9 @@ void emit_nonadv_stage(mhd_box* b, Emit& e, const StepArgs& a, bool first)
 }
 
 // ADV stage: the H and M groups rotate; B is read from its current slot
+// tail: run the tail of the step inside the last substage (the step itself)
 template <typename T, class Emit>
-void emit_adv_stage(mhd_box* b, Emit& e, const StepArgs& a)
+void emit_adv_stage(mhd_box* b, Emit& e, const StepArgs& a, bool tail = false)
 {
     int Sh = b->cur[GH], Sm = b->cur[GM], bb = b->cur[GB];
     Slots S0 = { Sh, Sm, bb };
@@ -560,9 +582,21 @@ void emit_adv_stage(mhd_box* b, Emit& e, const StepArgs& a)
     Slots B2 = { (Sh + 2) % 3, (Sm + 2) % 3, bb };
     emit_adv_substage<T>(b, e, S0, S0, A, a, rk_coef[0], 0);
     emit_adv_substage<T>(b, e, A, S0, B2, a, rk_coef[1], 0);
-    emit_adv_substage<T>(b, e, B2, S0, A, a, rk_coef[2], 0);
+    emit_adv_substage<T>(b, e, B2, S0, A, a, rk_coef[2], 0, tail);
     b->cur[GH] = A.h;
     b->cur[GM] = A.m;
+}
+
+// dt from the per-block CFL speed maxima in b->part
+template <class Emit>
+void emit_reduce_dt(mhd_box* b, Emit& e, int nparts)
+{
+    BReduceDt::Args ra;
+    ra.part = b->part;
+    ra.nparts = nparts;
+    ra.cflh = b->p.cfl * (1.0 / (double)b->p.n[0]);
+    ra.dt = b->dt_dev;
+    e.template launch<BReduceDt>(MHD_K_REDUCE, 1, 0, ra);
 }
 
 template <typename T, class Emit>
@@ -577,12 +611,7 @@ void emit_tail(mhd_box* b, Emit& e, const StepArgs& a, int mode)
     ta.part = b->part;
     ta.flags = b->flags;
     e.template launch<BTail<T>>(MHD_K_TAIL, b->nblocks, 0, ta);
-    BReduceDt::Args ra;
-    ra.part = b->part;
-    ra.nparts = b->nblocks;
-    ra.cflh = b->p.cfl * (1.0 / (double)b->p.n[0]);
-    ra.dt = b->dt_dev;
-    e.template launch<BReduceDt>(MHD_K_REDUCE, 1, 0, ra);
+    emit_reduce_dt(b, e, b->nblocks);
 }
 
 int ilog2(int n)
@@ -676,8 +705,9 @@ void emit_step(mhd_box* b, Emit& e, const StepArgs& a)
 {
     if (b->grav) emit_poisson<T>(b, e);
     emit_nonadv_stage<T>(b, e, a, true);
-    emit_adv_stage<T>(b, e, a);
-    emit_tail<T>(b, e, a, 1);
+    // the tail of the step runs inside the last ADV launch
+    emit_adv_stage<T>(b, e, a, true);
+    emit_reduce_dt(b, e, ztile_blocks(b->g, ztile_of(b->g, NTH)));
 }
 
 // ---------------------------------------------------------------- single-box operations

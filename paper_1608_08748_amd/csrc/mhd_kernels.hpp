@@ -994,6 +994,57 @@ struct BFftYZ {
     }
 };
 
+// ---------------------------------------------------------------- tail of the step, per cell
+
+// The tail of the step for one cell (after ADV): H2 (and H+) clamped to the
+// cell's hydrogen, FP64 chemistry, heating/cooling, the pressure-gated
+// dual-energy sync (Sec. 2.8); E, e, h2, hp in and out, each output rounded
+// to the storage type T as it is stored.  The caller stores E only with
+// heating/cooling (nothing else changes it).
+template <typename T>
+__device__ __forceinline__ void tail_cell(const StepArgs& a, const ChemArgs& ch, double rho, double mx, double my,
+                                          double mz, double bx, double by, double bz, double& E, double& e, double& h2,
+                                          double& hp)
+{
+    const int ion = a.ion;
+    const double dt = step_dt(a);
+    h2 = h2 > rho ? rho : h2;
+    h2 = h2 < 0.0 ? 0.0 : h2;
+    if (ion) {
+        hp = hp > rho - h2 ? rho - h2 : hp;
+        hp = hp < 0.0 ? 0.0 : hp;
+    }
+    if (ch.on) {
+        if (ion) chem_ion(ch, rho, e, h2, hp, dt, h2, hp);
+        else h2 = chem_h2(ch, a.gamma, rho, e, h2, dt);
+    }
+    if (ch.cool) {
+        double en = ion ? cooled_e_ion(ch, rho, e, h2, hp, dt) : cooled_e(ch, a.gamma, rho, e, h2, dt);
+        E += en - e;
+        e = en;
+        E = (double)(T)E;
+    }
+    double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+    double M = 0.5 * (bx * bx + by * by + bz * bz);
+    double ei = E - K - M;
+    if (ei >= 1e-3 * E && (gamma_cell(ion, a.gamma, rho, h2, hp) - 1.0) * ei > M) e = ei;
+    e = (double)(T)e;
+    h2 = (double)(T)h2;
+    if (ion) hp = (double)(T)hp;
+}
+
+// validity of a cell (flag bit 0 when not) and its CFL signal speed (zero
+// for an invalid cell)
+__device__ __forceinline__ double tail_speed(const StepArgs& a, double rho, double mx, double my, double mz, double E,
+                                             double e, double bx, double by, double bz, double h2, double hp,
+                                             uint32_t* flags)
+{
+    bool ok = rho > 0.0 && e > 0.0 && isfinite(rho) && isfinite(e) && isfinite(E) && isfinite(mx) && isfinite(my) &&
+              isfinite(mz) && isfinite(bx) && isfinite(by) && isfinite(bz);
+    if (!ok) atomicOr(flags, 1u);
+    return ok ? cell_speed(gamma_cell(a.ion, a.gamma, rho, h2, hp), rho, mx, my, mz, e, bx, by, bz) : 0.0;
+}
+
 // ---------------------------------------------------------------- ADV
 
 // ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, NQ x
@@ -1176,12 +1227,24 @@ struct AdvZArgs {
     RK rk;
     int dbg;
     ZTile zt;
+    // the tail of the step (TAIL launches only)
+    ChemArgs ch;
+    double* part;
+    uint32_t* flags;
 };
 
-template <typename T, int Q0, int NQ>
+// TAIL (the field group E, e, h2 [, hp] of the step's last substage): the
+// tail of the step runs on each cell as its new values are formed (rho and m
+// are the substage's outputs of the first group, launched before; B is not
+// changed by ADV), and the block's CFL speed maximum goes to part[blk]; the
+// same arithmetic as BTail after the update.
+template <typename T, int Q0, int NQ, bool TAIL = false>
 struct BAdvZUpdate {
     static constexpr int NT = NTH;
     static constexpr bool XCD = false;
+    static_assert(!TAIL || Q0 == 4, "the tail runs with the energy group");
+    static constexpr int MINW = TAIL ? 2 : 1;
+    static constexpr int UNROLL = TAIL ? 1 : 2;   // cells per trip of the march
     using Args = AdvZArgs<T>;
     // Along the march each cell's limited slope, lower interface value and
     // parabola are formed once: for the face between window slots 2 and 3
@@ -1215,10 +1278,15 @@ struct BAdvZUpdate {
     }
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
+        int i, j, x0, x1;
+        double smax = 0.0;
+        if (ztile_cell(A.g, A.zt, blk, tid, i, j, x0, x1)) march(A, i, j, x0, x1, smax);
+        if constexpr (TAIL) block_max_store(smax, A.part, blk);
+    }
+    static __device__ __forceinline__ void march(const Args& A, int i, int j, int x0, int x1, double& smax)
+    {
         const Geo& g = A.g;
         const int nd = g.nz;
-        int i, j, x0, x1;
-        if (!ztile_cell(g, A.zt, blk, tid, i, j, x0, x1)) return;
         const size_t N = (size_t)g.n;
         const int base = i + g.nx * j;
         const int stride = g.nxy;
@@ -1293,8 +1361,9 @@ struct BAdvZUpdate {
         };
         fetch(x0);
         // two cells per trip halve the register moves of the window slide
-        // (measured faster here; the face marches lose by it)
-#pragma unroll 2
+        // (measured faster here; the face marches lose by it); one with the
+        // tail, whose chemistry would double the registers
+#pragma unroll UNROLL
         for (int x = x0; x < x1; x++) {
             // slide: window slots 0..5 = cells x-2 .. x+3
 #pragma unroll
@@ -1328,22 +1397,55 @@ struct BAdvZUpdate {
                 dy[q] = A.Fy[o + cyp] - A.Fy[o + c];
                 sv[q] = A.S.f[fld[Q0 + q]][c];
             }
+            // the tail's inputs: the first group's new rho and m, the face
+            // field at the cell's lower and upper faces
+            T tr[4], tb[6];
+            if constexpr (TAIL) {
+                tr[0] = A.O.f[RHO][c];
+                tr[1] = A.O.f[MX][c];
+                tr[2] = A.O.f[MY][c];
+                tr[3] = A.O.f[MZ][c];
+                tb[0] = A.O.f[BX][c];
+                tb[1] = A.O.f[BX][cxp];
+                tb[2] = A.O.f[BY][c];
+                tb[3] = A.O.f[BY][cyp];
+                tb[4] = A.O.f[BZ][c];
+                tb[5] = A.O.f[BZ][c + (wrapc(x + 1, nd) - x) * stride];
+            }
             // upper face of cell x: between slots 2 (cell x) and 3 (cell x+1)
-            T Fup[NQ];
+            T Fup[NQ], nv[NQ];
             zflux(w, velocity(), ydx, pR, pdq, p6, d1, f1, Fup);
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 T dz = Fup[q] - Flo[q];
                 T inc = -dtdx * ((dx[q] + dy[q]) + dz);
-                int f = fld[Q0 + q];
                 if (A.dbg) {
-                    A.O.f[f][c] = inc;
+                    nv[q] = inc;
                 } else {
                     T u = w[q][2];
-                    A.O.f[f][c] = (u + ra * (sv[q] - u)) + rb * inc;
+                    nv[q] = (u + ra * (sv[q] - u)) + rb * inc;
                 }
                 Flo[q] = Fup[q];
             }
+            if constexpr (TAIL) {
+                // group fields E, e, h2 (, hp)
+                const double rho = (double)tr[0], mx = (double)tr[1], my = (double)tr[2], mz = (double)tr[3];
+                const double bx = 0.5 * ((double)tb[0] + (double)tb[1]);
+                const double by = 0.5 * ((double)tb[2] + (double)tb[3]);
+                const double bz = 0.5 * ((double)tb[4] + (double)tb[5]);
+                double E = (double)nv[0], e = (double)nv[1], h2 = (double)nv[2];
+                double hp = 0.0;
+                if constexpr (NQ > 3) hp = (double)nv[3];
+                tail_cell<T>(A.a, A.ch, rho, mx, my, mz, bx, by, bz, E, e, h2, hp);
+                nv[0] = (T)E;
+                nv[1] = (T)e;
+                nv[2] = (T)h2;
+                if constexpr (NQ > 3) nv[3] = (T)hp;
+                const double spd = tail_speed(A.a, rho, mx, my, mz, E, e, bx, by, bz, h2, hp, A.flags);
+                smax = spd > smax ? spd : smax;
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; q++) A.O.f[fld[Q0 + q]][c] = nv[q];
             if (Q0 == 0 && A.dbg) {
                 A.O.f[BX][c] = T(0);
                 A.O.f[BY][c] = T(0);
@@ -1355,9 +1457,10 @@ struct BAdvZUpdate {
 
 // ---------------------------------------------------------------- tail and reductions
 
-// Tail of the step (after ADV): H2 clamp to [0, rho], chemistry, dual-energy
-// sync (Sec. 2.8, pressure-gated), validity flag, per-block CFL speed maximum.
-// mode: 1 = full tail, 0 = speed only (state unchanged).
+// Tail of the step (after ADV) as a pass of its own: tail_cell on every cell,
+// validity flag, per-block CFL speed maximum.  mode: 1 = full tail, 0 = speed
+// only (state unchanged).  The step itself runs the tail inside its last ADV
+// launch (BAdvZUpdate with TAIL).
 template <typename T>
 struct BTail {
     static constexpr int NT = NTH;
@@ -1391,41 +1494,13 @@ struct BTail {
             double h2 = (double)U.f[H2][c];
             double hp = ion ? (double)U.f[HP][c] : 0.0;
             if (A.mode == 1) {
-                const double dt = step_dt(A.a);
-                h2 = h2 > rho ? rho : h2;
-                h2 = h2 < 0.0 ? 0.0 : h2;
-                if (ion) {
-                    hp = hp > rho - h2 ? rho - h2 : hp;
-                    hp = hp < 0.0 ? 0.0 : hp;
-                }
-                if (A.ch.on) {
-                    if (ion) chem_ion(A.ch, rho, e, h2, hp, dt, h2, hp);
-                    else h2 = chem_h2(A.ch, A.a.gamma, rho, e, h2, dt);
-                }
-                if (A.ch.cool) {
-                    double en = ion ? cooled_e_ion(A.ch, rho, e, h2, hp, dt) : cooled_e(A.ch, A.a.gamma, rho, e, h2, dt);
-                    E += en - e;
-                    e = en;
-                    U.f[EN][c] = (T)E;
-                    E = (double)(T)E;
-                }
-                double K = 0.5 * (mx * mx + my * my + mz * mz) / rho;
-                double M = 0.5 * (bx * bx + by * by + bz * bz);
-                double ei = E - K - M;
-                if (ei >= 1e-3 * E && (gamma_cell(ion, A.a.gamma, rho, h2, hp) - 1.0) * ei > M) e = ei;
+                tail_cell<T>(A.a, A.ch, rho, mx, my, mz, bx, by, bz, E, e, h2, hp);
+                if (A.ch.cool) U.f[EN][c] = (T)E;
                 U.f[H2][c] = (T)h2;
                 U.f[EI][c] = (T)e;
-                e = (double)(T)e;
-                h2 = (double)(T)h2;
-                if (ion) {
-                    U.f[HP][c] = (T)hp;
-                    hp = (double)(T)hp;
-                }
+                if (ion) U.f[HP][c] = (T)hp;
             }
-            bool ok = rho > 0.0 && e > 0.0 && isfinite(rho) && isfinite(e) && isfinite(E) && isfinite(mx) &&
-                      isfinite(my) && isfinite(mz) && isfinite(bx) && isfinite(by) && isfinite(bz);
-            if (!ok) atomicOr(A.flags, 1u);
-            spd = ok ? cell_speed(gamma_cell(ion, A.a.gamma, rho, h2, hp), rho, mx, my, mz, e, bx, by, bz) : 0.0;
+            spd = tail_speed(A.a, rho, mx, my, mz, E, e, bx, by, bz, h2, hp, A.flags);
         }
         block_max_store(spd, A.part, blk);
     }
