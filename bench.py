@@ -7,8 +7,11 @@ substages: face Riemann solves along y, z, then x fused with the update of
 m, E, e, then the face-field update from edge fields), ADV stage (3 RK
 substages: face fluxes along x, y, then z fused with the update; the last
 substage's energy-group launch also runs the tail: H2 clamp, FP64
-chemistry, FP64 regularisation, CFL speed) and the CFL reduction.  The timed region is K x {dt = cfl_dt(); step(dt)} with the state
-resident in HBM, bracketed by device synchronisation.
+chemistry, FP64 regularisation, CFL speed) and the CFL reduction.  The
+timed region is K steps, each at the CFL dt the previous step's reduction
+left on the device (mhd_step_cfl; c3's FP32 run replays the dt sequence of
+its FP64 run), with the state resident in HBM, bracketed by device
+synchronisation.
 
 Workloads (synthetic, seeded; see paper_1608_08748_amd/inputs.py):
   c2  256^3 FP64, rms Mach 5, beta 1, x_H2 1e-3, seed 2   (default)
@@ -75,15 +78,23 @@ def _copy_calibration(nbytes=1 << 30):
     del a, b
 
 
-def _timed_run(box, steps, dts=None):
+def _timed_run(box, steps, dts=None, record=False):
+    """K steps: with the given dt sequence, else each at its CFL dt.  Without
+    `record` the CFL dt stays on the device (mhd_step_cfl, no host round trip
+    per step); with it every dt is read back and returned."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     used = []
     for s in range(steps):
-        dt = box.cfl_dt() if dts is None else dts[s]
-        box.step(dt)
-        used.append(dt)
+        if dts is not None:
+            box.step(dts[s])
+        elif record:
+            dt = box.cfl_dt()
+            box.step(dt)
+            used.append(dt)
+        else:
+            box.step_cfl()
     box.cfl_dt()            # waits for the last step
     torch.cuda.synchronize()
     return time.perf_counter() - t0, used
@@ -288,8 +299,9 @@ def _largest_box_bench(args):
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for s in range(steps):
-        box.step(box.cfl_dt())
+        box.step_cfl()
         if s % 10 == 9:
+            box.cfl_dt()    # waits, so the progress line follows the device
             log("step %d" % (s + 1))
     box.cfl_dt()
     torch.cuda.synchronize()
@@ -378,7 +390,7 @@ def main():
         torch.cuda.empty_cache()
         ref = binding.Box(shape, precision=binding.FP64, cooling=cool, grav_G=gG, ionisation=ion)
         ref.init_state(W)
-        el64, ref_dts = _timed_run(ref, steps)
+        el64, ref_dts = _timed_run(ref, steps, record=True)
         t64 = ref.totals()
         G64 = ref.get_state()
         absq = np.abs(G64).reshape(binding.NFIELDS, -1).sum(axis=1)

@@ -190,9 +190,10 @@ enum {
 };
 
 /* Enable (1) or disable (0) per-launch HIP-event timing of the step's
- * kernels on the box's stream; enabling clears the accumulators.  While
- * enabled, each mhd_step / mhd_step_cfl waits for its own last kernel
- * (so the step becomes synchronous). */
+ * kernels on the box's stream; enabling clears the accumulators.  Steps stay
+ * asynchronous: the events of up to 1024 launches are held, and a step waits
+ * for the recorded ones only once 512 are pending (about every 20 steps);
+ * mhd_get_timing waits for all of them. */
 int mhd_set_timing(mhd_box *b, int enable);
 
 /* Accumulated device time (ms) and launch count per kernel class since

@@ -38,6 +38,10 @@ using namespace mhd;
 
 // ---------------------------------------------------------------- box
 
+// launches whose event pairs the timing ring holds (a step makes at most a
+// few dozen)
+constexpr int EVCAP = 1024;
+
 struct mhd_box {
     mhd_params p;
     Geo g;
@@ -59,8 +63,8 @@ struct mhd_box {
     // per-launch event timing (mhd_set_timing)
     int timing;
     int nev;
-    hipEvent_t ev[2 * 64];
-    int evcls[64];
+    hipEvent_t ev[2 * EVCAP];
+    int evcls[EVCAP];
     int ev_ready;
     double tms[MHD_NKCLASS];
     int64_t tcnt[MHD_NKCLASS];
@@ -277,7 +281,7 @@ struct KTimer {
     int slot;
     KTimer(mhd_box* box, int cls) : b(box), slot(-1)
     {
-        if (b && b->timing && b->nev < 64) {
+        if (b && b->timing && b->nev < EVCAP) {
             slot = b->nev++;
             b->evcls[slot] = cls;
             (void)hipEventRecord(b->ev[2 * slot], b->s);
@@ -720,7 +724,9 @@ int full_step(mhd_box* b, double dt, bool dev)
     emit_step<T>(b, e, a);
     int st = launch_status();
     if (st) return st;
-    return timing_collect(b);
+    // the event ring is read (a wait on its last event) only once half of it
+    // is used, so timed steps stay asynchronous
+    return b->nev >= EVCAP / 2 ? timing_collect(b) : MHD_OK;
 }
 
 int sync_and_flags(mhd_box* b)
@@ -1174,7 +1180,7 @@ int mhd_set_timing(mhd_box* b, int enable)
 {
     if (!b) return MHD_EINVAL;
     if (enable && !b->ev_ready) {
-        for (int i = 0; i < 2 * 64; i++)
+        for (int i = 0; i < 2 * EVCAP; i++)
             if (hipEventCreate(&b->ev[i]) != hipSuccess) return MHD_EDEVICE;
         b->ev_ready = 1;
     }
@@ -1274,7 +1280,7 @@ int mhd_debug_stage(mhd_box* b, int stage, double dt)
 int mhd_destroy(mhd_box* b)
 {
     if (b && b->ev_ready)
-        for (int i = 0; i < 2 * 64; i++) (void)hipEventDestroy(b->ev[i]);
+        for (int i = 0; i < 2 * EVCAP; i++) (void)hipEventDestroy(b->ev[i]);
     delete b;
     return MHD_OK;
 }
