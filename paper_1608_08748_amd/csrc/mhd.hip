@@ -503,14 +503,22 @@ void emit_adv_face(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a)
         ma.seg = b->g.ny < SEG ? b->g.ny : SEG;
         long long threads = (long long)b->g.nx * b->g.nz * ((b->g.ny + ma.seg - 1) / ma.seg);
         e.template launch<BAdvFaceMarchY<T, NQ>>(MHD_K_ADV_FACE, (int)((threads + NTH - 1) / NTH), 0, ma);
-        return;
+    } else {
+        // x faces from row segments staged in LDS
+        static_assert(D == 0, "y faces are marched");
+        typename BAdvFaceXRow<T, NQ>::Args fa;
+        const Geo& g = b->g;
+        fa.g = g;
+        fa.U = cview(in);
+        fa.a = a;
+        fa.F = reinterpret_cast<T*>(b->F[0]);
+        fa.tx = g.nx < NTH ? g.nx : NTH;
+        fa.spr = (g.nx + fa.tx - 1) / fa.tx;
+        fa.rpb = NTH / fa.tx < NTH / 6 ? NTH / fa.tx : NTH / 6;   // 6 halo cells per segment, one per thread
+        const long long nseg = (long long)g.ny * g.nz * fa.spr;
+        const size_t shm = (size_t)NQ * fa.rpb * (fa.tx + 6) * sizeof(T);
+        e.template launch<BAdvFaceXRow<T, NQ>>(MHD_K_ADV_FACE, (int)((nseg + fa.rpb - 1) / fa.rpb), shm, fa);
     }
-    typename BAdvFace<T, D, NQ>::Args fa;
-    fa.g = b->g;
-    fa.U = cview(in);
-    fa.a = a;
-    fa.F = reinterpret_cast<T*>(b->F[D]);
-    e.template launch<BAdvFace<T, D, NQ>>(MHD_K_ADV_FACE, b->nblocks, 0, fa);
 }
 
 
@@ -523,9 +531,10 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
-    // x faces one per thread (an LDS row scheme that computes each cell's
-    // slopes once measured slower: block barriers, fewer waves); y faces
-    // marched along y, each cell's parabola formed once
+    // x faces from staged row segments, one face per thread (an LDS row
+    // scheme that computes each cell's slopes once measured slower: block
+    // barriers, fewer waves); y faces marched along y, each cell's parabola
+    // formed once
     if (b->p.ionisation) {
         emit_adv_face<T, 0, 8>(b, e, in, a);
         emit_adv_face<T, 1, 8>(b, e, in, a);

@@ -1047,47 +1047,89 @@ __device__ __forceinline__ double tail_speed(const StepArgs& a, double rho, doub
 
 // ---------------------------------------------------------------- ADV
 
-// ADV fluxes at the lower face of every cell along D (Sec. 2.6): outputs, NQ x
-// N (NQ = 7, or 8 with the ionisation network), in the order rho, mx, my, mz,
-// E, e, h2, hp.
-template <typename T, int D, int NQ>
-struct BAdvFace {
+// ADV fluxes at the lower x face of every cell (Sec. 2.6): the sqrt(rho)-
+// weighted face velocity and the upwind parabola average of NQ fields (NQ =
+// 7, or 8 with the ionisation network), in the order rho, mx, my, mz, E, e,
+// h2, hp; outputs NQ x N.  A block holds rpb segments of tx cells of x rows
+// (whole rows when nx <= 256, else 256-cell pieces), each with three cells of
+// its periodic row on either side, loaded coalesced into LDS behind one
+// barrier; each thread then forms its face from the staged row, its 5-cell
+// window read at fixed offsets (no per-neighbour wrap or address
+// arithmetic).  Dynamic LDS: NQ x rpb x (tx + 6) values.
+template <typename T, int NQ>
+struct BAdvFaceXRow {
     static constexpr int NT = NTH;
-    static constexpr bool XCD = D == 1;   // the y stencil reads rows of neighbouring blocks
+    static constexpr bool XCD = false;
     struct Args {
         Geo g;
         CFields<T> U;
         T* F;
         StepArgs a;
+        int tx, rpb, spr;   // segment width, segments per block, segments per row
     };
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
+        extern __shared__ unsigned char smem_raw[];
+        T* L = reinterpret_cast<T*>(smem_raw);
         const Geo& g = A.g;
-        int c = blk * NT + tid;
-        if (c >= g.n) return;
-        int i, j, k;
-        decompose(g, c, i, j, k);
-        const size_t N = (size_t)g.n;
-        const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
-        int idx[6];
-#pragma unroll
-        for (int m = 0; m < 6; m++) idx[m] = nbr<D>(g, c, i, j, k, m - 3);
-        // sqrt(rho)-weighted face velocity; sqrt(rho) v = m / sqrt(rho)
-        T rl = A.U.f[RHO][idx[2]], rr = A.U.f[RHO][c];
-        T rsl = rsqrt_nr(rl), rsr = rsqrt_nr(rr);
-        T vf = (A.U.f[MX + D][idx[2]] * rsl + A.U.f[MX + D][c] * rsr) * rcp_nr(rl * rsl + rr * rsr);
-        bool upw = vf >= T(0);
-        T y = upw ? ydx * vf : ydx * (-vf);
+        const int nx = g.nx, tx = A.tx, cw = tx + 6;
+        const int LS = A.rpb * cw;   // staged cells per field
+        const int nseg = g.ny * g.nz * A.spr;   // below 2^31: at most one segment per cell
         const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
+        // own cell
+        const int sl = tid / tx, pos = tid - sl * tx;
+        const int sg = blk * A.rpb + sl;
+        bool act = false;
+        size_t c = 0;
+        int p = 0;
+        if (sl < A.rpb && sg < nseg) {
+            const int row = sg / A.spr, s0 = (sg - row * A.spr) * tx;
+            const int w = min(tx, nx - s0);
+            if (pos < w) {
+                act = true;
+                c = (size_t)row * nx + s0 + pos;
+                p = sl * cw + pos + 3;
+#pragma unroll
+                for (int q = 0; q < NQ; q++) L[q * LS + p] = A.U.f[fld[q]][c];
+            }
+        }
+        // halo: three cells of the periodic row on each side of each segment
+        if (tid < 6 * A.rpb) {
+            const int hs = tid / 6, k = tid - 6 * hs;
+            const int hg = blk * A.rpb + hs;
+            if (hg < nseg) {
+                const int row = hg / A.spr, s0 = (hg - row * A.spr) * tx;
+                const int w = min(tx, nx - s0);
+                const int x = k < 3 ? s0 - 3 + k : s0 + w + k - 3;
+                const int hp = hs * cw + (k < 3 ? k : w + k);
+                const size_t hc = (size_t)row * nx + wrapc(x, nx);
+#pragma unroll
+                for (int q = 0; q < NQ; q++) L[q * LS + hp] = A.U.f[fld[q]][hc];
+            }
+        }
+        __syncthreads();
+        if (!act) return;
+        const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
+        // sqrt(rho)-weighted face velocity; sqrt(rho) v = m / sqrt(rho)
+        const T* rho = L;
+        const T* mx = L + LS;
+        const T rl = rho[p - 1], rr = rho[p];
+        const T rsl = rsqrt_nr(rl), rsr = rsqrt_nr(rr);
+        const T vf = (mx[p - 1] * rsl + mx[p] * rsr) * rcp_nr(rl * rsl + rr * rsr);
+        const bool upw = vf >= T(0);
+        const T y = upw ? ydx * vf : ydx * (-vf);
+        const int b = upw ? p - 3 : p - 2;
+        const size_t N = (size_t)g.n;
+        T out[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
-            const T* u = A.U.f[fld[q]];
-            int o = upw ? 0 : 1;
-            T q0 = u[idx[o]], q1 = u[idx[o + 1]], q2 = u[idx[o + 2]], q3 = u[idx[o + 3]], q4 = u[idx[o + 4]];
-            Par<T> P = parabola(q0, q1, q2, q3, q4);
+            const T* u = L + q * LS;
+            Par<T> P = parabola(u[b], u[b + 1], u[b + 2], u[b + 3], u[b + 4]);
             T qup = upw ? avg_right(P, y) : avg_left(P, y);
-            A.F[q * N + c] = vf * qup;
+            out[q] = vf * qup;
         }
+#pragma unroll
+        for (int q = 0; q < NQ; q++) A.F[q * N + c] = out[q];
     }
 };
 
@@ -1097,7 +1139,7 @@ struct BAdvFace {
 // per-face kernel forms three slopes, two interface values and a parabola per
 // face); the previous cell's right side and sqrt(rho) are carried.  The face
 // takes the upwind average: the left cell's right part for vf >= 0, the right
-// cell's left part otherwise (same arithmetic as BAdvFace).
+// cell's left part otherwise (the same arithmetic as the x faces).
 template <typename T, int NQ>
 struct BAdvFaceMarchY {
     static constexpr int NT = NTH;
