@@ -273,6 +273,12 @@ struct BFaceXRows {
     static constexpr int NT = MAXT;
     static constexpr bool XCD = false;
     using Args = FaceArgs<T>;
+    // LDS slot of component k (qR, dq, q6) of variable v's published right
+    // side: slots 0-7 and 14-23, around the slopes in 8-13
+    static __device__ __forceinline__ constexpr int sslot(int v, int k)
+    {
+        return 3 * v + k < 8 ? 3 * v + k : 3 * v + k + 6;
+    }
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
         extern __shared__ unsigned char smem_raw[];
@@ -335,41 +341,36 @@ struct BFaceXRows {
             }
         }
         __syncthreads();
-        // interface value at the lower face, from the left cell's slope
-        if (act) {
-#pragma unroll
-            for (int v = 0; v < 6; v++) {
-                fl[v] = interface_value(q1[v], q2[v], sm[(8 + v) * NT + tl], dm[v]);
-                sm[v * NT + tid] = fl[v];
-            }
-        }
-        __syncthreads();
-        // parabolas of the own cell (the upper interface value is the right
-        // cell's lower one); its right side is published in slots 6-23
-        // (primitives and slopes there are no longer read)
+        // interface values at both faces from the neighbours' slopes (the
+        // upper one is the right cell's lower one, formed from the same
+        // operands), then the own cell's parabolas; the right side is
+        // published in the slots sslot(v, 0..2) (0-7 and 14-23: the
+        // primitives, densities and gamma there are no longer read; the
+        // slopes in 8-13 are read until the barrier below)
         Side<T> R;
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                T fr = sm[v * NT + tr];
+                fl[v] = interface_value(q1[v], q2[v], sm[(8 + v) * NT + tl], dm[v]);
+                T fr = interface_value(q2[v], q3[v], dm[v], sm[(8 + v) * NT + tr]);
                 Par<T> P = parabola_finish(q0[v], q1[v], q2[v], q3[v], q4[v], fl[v], fr, dm[v]);
                 side_right(P, R, v);
-                sm[(6 + 3 * v + 0) * NT + tid] = P.qR;
-                sm[(6 + 3 * v + 1) * NT + tid] = P.dq;
-                sm[(6 + 3 * v + 2) * NT + tid] = P.q6;
+                sm[sslot(v, 0) * NT + tid] = P.qR;
+                sm[sslot(v, 1) * NT + tid] = P.dq;
+                sm[sslot(v, 2) * NT + tid] = P.q6;
             }
         }
         __syncthreads();
-        // the face solve; its fluxes go to slots 0-4 (the interface values
-        // there were read before the barrier)
+        // the face solve; its fluxes go to slots 8-12 (the slopes there were
+        // read before the barrier)
         T out[7];
         if (act) {
             Side<T> L;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                L.e[v] = sm[(6 + 3 * v + 0) * NT + tl];
-                L.dq[v] = sm[(6 + 3 * v + 1) * NT + tl];
-                L.q6[v] = sm[(6 + 3 * v + 2) * NT + tl];
+                L.e[v] = sm[sslot(v, 0) * NT + tl];
+                L.dq[v] = sm[sslot(v, 1) * NT + tl];
+                L.q6[v] = sm[sslot(v, 2) * NT + tl];
             }
             // parabola variables 3, 4, 5 are Bt1, Bt2, p
             face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
@@ -377,7 +378,7 @@ struct BFaceXRows {
             A.F[5 * N + c] = out[5];
             A.F[6 * N + c] = out[6];
 #pragma unroll
-            for (int v = 0; v < 5; v++) sm[v * NT + tid] = out[v];
+            for (int v = 0; v < 5; v++) sm[(8 + v) * NT + tid] = out[v];
         }
         __syncthreads();
         if (!act) return;
@@ -390,7 +391,7 @@ struct BFaceXRows {
         T dF[3][5];
 #pragma unroll
         for (int v = 0; v < 5; v++) {
-            dF[0][v] = sm[v * NT + tr] - out[v];
+            dF[0][v] = sm[(8 + v) * NT + tr] - out[v];
             if (FluxDiff<T>::v) {   // the marches stored per-cell differences
                 dF[1][v] = Fy[v * N + c];
                 dF[2][v] = Fz[v * N + c];
