@@ -123,7 +123,7 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 TRAFFIC = {
     # average of the x-row (with the m, E, e update), y-march and z-march
     # face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("f3ca7a335c5d35ac", 3307032672),
+    ("c2", 8, "nonadv_face"): ("8e96c4e1f50116b5", 3307925788),
 }
 
 
