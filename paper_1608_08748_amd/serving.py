@@ -1,4 +1,4 @@
-"""Serving driver: requests arrive (Poisson process or all at once), are
+"""Serving loop: requests arrive (Poisson process or all at once), are
 submitted to a ``binding.Server`` as they arrive, and the host loop calls
 ``progress`` (admission + one merged step of every box in flight, pipelined
 one round deep) until all requests have completed.  Latency is arrival to completion on the host clock;
