@@ -21,6 +21,12 @@ Workloads (synthetic, seeded; see paper_1608_08748_amd/inputs.py):
   c4  1024^3 FP32 single box (about 237 GB of HBM), conservation over the run
   c5  serving: 256 boxes of {32..128}^3 with Poisson arrivals, p50/p99 latency
 
+The default line (c2) also carries two legs of the metric: the FP32 form on
+the same 256^3 state and dt sequence with its total and field errors against
+the FP64 run (`fp32_leg`), and the serving workload with p50/p99 latency and
+served-FP32-vs-FP64 errors for a sample of requests (`serving_leg`);
+--no-legs leaves them out.
+
 Prints one JSON line.
 """
 import argparse
@@ -191,19 +197,40 @@ def _cpu_baseline(n=192, steps=3, cooling=False, grav_G=0.0, ionisation=False):
                " with the ionisation network" if ionisation else "", n, steps, el)}
 
 
-def _serving_bench(args):
+def _field_errors(A, B, nf):
+    """Per-field L1 and L-inf differences of state A against reference B, each
+    relative to the reference field's L1 norm and max-abs value."""
+    import numpy as np
+    from paper_1608_08748_amd import binding
+    out = {}
+    for f in range(nf):
+        d = np.abs(A[f] - B[f])
+        out[binding.FIELDS[f]] = {"l1": float(d.sum() / max(np.abs(B[f]).sum(), 1e-300)),
+                                  "linf": float(d.max() / max(np.abs(B[f]).max(), 1e-300))}
+    return out
+
+
+def _total_errors(ta, tb, absq, nf):
+    """|total(A) - total(B)| / sum |q_B| per field."""
+    from paper_1608_08748_amd import binding
+    return {binding.FIELDS[f]: float(abs(ta[f] - tb[f]) / absq[f]) for f in range(nf) if absq[f] > 0}
+
+
+def _serving(requests, steps, budget_run=False, sample=4):
     """c5: requests with sizes {32,48,64,96,128}^3, rms Mach U[1,10], beta
-    U[0.1,10], x_H2 log-uniform [1e-4,1e-1], 50 steps each, FP32 state with FP64
-    chemistry; saturated run (all at t = 0) for the capacity, then Poisson
-    arrivals at 0.8 of it for the latencies, then a 2 GB budget.  Request states
-    sit in pinned host memory and are lent to the server (no copy at
-    submission; one DMA each at admission)."""
+    U[0.1,10], x_H2 log-uniform [1e-4,1e-1], `steps` steps each, FP32 state
+    with FP64 chemistry; saturated run (all at t = 0) for the capacity, then
+    Poisson arrivals at 0.8 of it for the latencies (and, with budget_run, a
+    2 GB HBM budget).  Request states sit in pinned host memory and are lent
+    to the server (no copy at submission; one DMA each at admission).  For
+    `sample` requests of distinct sizes the served FP32 result is compared
+    with the plain FP64 step of the same request on the same GPU (each at its
+    own CFL steps)."""
     import numpy as np
     import torch
     from paper_1608_08748_amd import binding, inputs, serving
-    steps = args.steps if args.steps is not None else 50
     torch.cuda.set_device(0)
-    reqs = inputs.serving_requests(count=args.requests, seed=5)
+    reqs = inputs.serving_requests(count=requests, seed=5)
     t = time.perf_counter()
     states = [inputs.request_state(r) for r in reqs]
     gen_s = time.perf_counter() - t
@@ -216,14 +243,20 @@ def _serving_bench(args):
     states = pinned
     pin_s = time.perf_counter() - t
     mean_cells = float(np.mean([r["n"] ** 3 for r in reqs]))
+    # the first request of each size, smallest sizes first
+    first = {}
+    for i, r in enumerate(reqs):
+        first.setdefault(r["n"], i)
+    keep = [first[n] for n in sorted(first)][:sample]
 
-    def one(budget, slots, arrivals):
+    def one(budget, slots, arrivals, keep_idx=()):
         sv = binding.Server(budget, max_slots=slots, precision=binding.FP32_MIXED)
-        out = serving.run(sv, states, steps, arrivals=arrivals, borrow=True)
+        out = serving.run(sv, states, steps, arrivals=arrivals, borrow=True, keep_state=set(keep_idx))
+        kept = {i: sv.result(out["records"][i]["id"]) for i in keep_idx}
         _, peak, cap = sv.memory()
         sv.close()
         torch.cuda.empty_cache()
-        out.pop("records")
+        out["kept"] = kept
         out["peak_pool_bytes"] = peak
         out["pool_bytes"] = cap
         return out
@@ -236,27 +269,64 @@ def _serving_bench(args):
     sat = one(budget, slots, None)
     req_rate = 0.8 * sat["throughput"] / (mean_cells * steps)
     arr = serving.poisson_arrivals(len(states), req_rate, seed=5)
-    poi = one(budget, slots, arr)
-    small = one(2 << 30, slots, None)
+    poi = one(budget, slots, arr, keep)
+    # served FP32 against the plain FP64 step of the same requests
+    cmp = []
+    for i in keep:
+        W = states[i]
+        box = binding.Box(W.shape[1:], precision=binding.FP64)
+        box.init_state(W)
+        for _ in range(steps):
+            box.step_cfl()
+        G64, t64 = box.get_state(), box.totals()
+        box.close()
+        G32 = poi["kept"][i]
+        t32 = np.asarray(poi["records"][i]["totals"])
+        absq = np.abs(G64).reshape(binding.NFIELDS, -1).sum(axis=1)
+        te = _total_errors(t32, t64, absq, binding.NFIELDS - 1)
+        fe = _field_errors(G32, G64, binding.NFIELDS - 1)
+        cmp.append({"request": i, "n": reqs[i]["n"], "mach": round(reqs[i]["mach"], 3),
+                    "beta": round(reqs[i]["beta"], 3), "max_total_rel_err": max(te.values()),
+                    "total_rel_err": te, "max_field_l1_rel": max(v["l1"] for v in fe.values()),
+                    "max_field_linf_rel": max(v["linf"] for v in fe.values())})
+    torch.cuda.empty_cache()
+    keys = ("throughput", "span_s", "rounds", "max_active", "statuses", "latency_p50", "latency_p99",
+            "latency_mean", "peak_pool_bytes")
+    res = {
+        "value": round(poi["throughput"], 1), "unit": "cell-updates/s", "requests": len(states), "steps": steps,
+        "latency_p50_s": round(poi["latency_p50"], 4), "latency_p99_s": round(poi["latency_p99"], 4),
+        "arrival_rate_per_s": round(req_rate, 3), "hbm_budget_bytes": budget, "max_slots": slots,
+        "poisson": {k: poi[k] for k in keys},
+        "saturated": {k: sat[k] for k in keys},
+        "fp32_vs_fp64": {"what": "served FP32 result after %d steps against the plain FP64 step of the same "
+                                 "request (single box, FP64 state), each at its own CFL steps; totals relative to "
+                                 "sum |q|, fields L1 relative to the field's L1 norm, L-inf to its max" % steps,
+                         "gate_total_rel": 1e-5,
+                         "max_total_rel_err": max(c["max_total_rel_err"] for c in cmp) if cmp else None,
+                         "requests": cmp},
+        "ic_generation_s": round(gen_s, 1), "pinning_s": round(pin_s, 1),
+    }
+    if budget_run:
+        small = one(2 << 30, slots, None)
+        res["budget_2GB"] = {k: small[k] for k in keys + ("pool_bytes",)}
+    return res
+
+
+def _serving_bench(args):
+    """The serving workload as the line's headline."""
+    steps = args.steps if args.steps is not None else 50
+    sv = _serving(args.requests, steps, budget_run=True)
     return {
-        "metric": METRIC, "value": round(poi["throughput"], 1), "unit": "cell-updates/s",
+        "metric": METRIC, "value": sv["value"], "unit": "cell-updates/s",
         "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "c5: %d requests, boxes {32,48,64,96,128}^3, rms Mach U[1,10], beta U[0.1,10], "
                                "x_H2 log-uniform [1e-4,1e-1], %d steps each, FP32 state + FP64 chemistry, "
-                               "Poisson arrivals at 0.8 x saturated capacity" % (len(states), steps),
-                   "hbm_budget_bytes": budget, "max_slots": slots, "request_states": "pinned host memory, lent",
+                               "Poisson arrivals at 0.8 x saturated capacity" % (sv["requests"], steps),
+                   "hbm_budget_bytes": sv["hbm_budget_bytes"], "max_slots": sv["max_slots"],
+                   "request_states": "pinned host memory, lent",
                    "parallelism": "single GPU, merged multi-box launches"},
-        "step_roofline": _step_roofline(poi["throughput"], 4),
-        "latency_p50_s": round(poi["latency_p50"], 4), "latency_p99_s": round(poi["latency_p99"], 4),
-        "arrival_rate_per_s": round(req_rate, 3),
-        "poisson": {k: poi[k] for k in ("throughput", "span_s", "rounds", "max_active", "statuses", "latency_mean",
-                                        "peak_pool_bytes")},
-        "saturated": {k: sat[k] for k in ("throughput", "span_s", "rounds", "max_active", "statuses",
-                                          "latency_p50", "latency_p99", "peak_pool_bytes")},
-        "budget_2GB": {k: small[k] for k in ("throughput", "span_s", "rounds", "max_active", "statuses",
-                                             "latency_p50", "latency_p99", "peak_pool_bytes", "pool_bytes")},
-        "ic_generation_s": round(gen_s, 1), "pinning_s": round(pin_s, 1),
+        "serving": sv,
     }
 
 
@@ -329,6 +399,49 @@ def _largest_box_bench(args):
     }
 
 
+def _precision_leg(W, shape, steps, warmup, dts, G64, t64, phys, workload):
+    """FP32 state on the workload's state, replaying the FP64 run's dt
+    sequence: throughput, per-kernel time, and the errors of every total and
+    field against that FP64 run."""
+    import numpy as np
+    import torch
+    from paper_1608_08748_amd import binding
+    box = binding.Box(shape, precision=binding.FP32_MIXED, **phys)
+    box.init_state(W)
+    for s in range(warmup):
+        box.step(dts[s % len(dts)])
+    box.init_state(W)
+    box.set_timing(True)
+    el, _ = _timed_run(box, steps, dts)
+    timing = box.get_timing()
+    box.set_timing(False)
+    t32 = box.totals()
+    G32 = box.get_state()
+    box.close()
+    del box
+    torch.cuda.empty_cache()
+    nf = binding.NFIELDS if phys.get("ionisation") else binding.NFIELDS - 1
+    ncell = int(np.prod(shape))
+    absq = np.abs(G64).reshape(binding.NFIELDS, -1).sum(axis=1)
+    te = _total_errors(t32, t64, absq, nf)
+    fe = _field_errors(G32, G64, nf)
+    del G32
+    return {
+        "value": round(ncell * steps / el, 1), "unit": "cell-updates/s", "ms_per_step": round(el / steps * 1e3, 3),
+        "dtype": "f32+f64", "steps": steps,
+        "what": "FP32 state and fluxes with FP64 chemistry, regularisation, CFL and totals, on the same initial "
+                "state and dt sequence as the FP64 run; errors against that FP64 run: totals relative to sum |q|, "
+                "fields L1 relative to the field's L1 norm and L-inf relative to its max",
+        "roofline": _roofline(timing, ncell, 4, workload),
+        "step_roofline": _step_roofline(ncell * steps / el, 4),
+        "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
+        "gate_total_rel": 1e-5,
+        "max_total_rel_err": max(te.values()),
+        "total_rel_err": te,
+        "fp32_field_err": fe,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +450,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="c2: leave out the FP32 and serving legs of the line")
     ap.add_argument("--cooling", action="store_true",
                     help="c1-c3: add the heating/cooling stage (Sec. 2 stage 5) after chemistry")
     ap.add_argument("--gravity", action="store_true",
@@ -353,6 +468,9 @@ def main():
     import numpy as np
     import torch
     from paper_1608_08748_amd import binding
+
+    def log(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
 
     if args.config == "c5":
         print(json.dumps(_serving_bench(args)), flush=True)
@@ -376,59 +494,89 @@ def main():
     ion = bool(args.ionisation)
     if ion:
         cfg["desc"] += " + ionisation network (H+ from zero)"
-    box = binding.Box(shape, precision=cfg["precision"], cooling=cool, grav_G=gG, ionisation=ion)
-    box.init_state(W)
-    for _ in range(args.warmup):
-        box.step(box.cfl_dt())
-    box.init_state(W)      # timed run starts from the initial condition
+    phys = dict(cooling=cool, grav_G=gG, ionisation=ion)
+    workload = args.config + ("+gravity" if gG > 0 else "") + ("+ionisation" if ion else "")
+    esz = 8 if cfg["precision"] == binding.FP64 else 4
+    legs = args.config == "c3" or (args.config == "c2" and not args.no_legs)
 
-    ref_dts = None
+    # the FP64 run with its dt sequence read back each step: the reference of
+    # the FP32 errors (c3's FP64 figure is this run's rate)
+    ref_dts = G64 = t64 = None
     extra = {}
-    if args.config == "c3":
-        # the FP64 run of the same seed first; the FP32 run replays its dt sequence
-        del box
-        torch.cuda.empty_cache()
-        ref = binding.Box(shape, precision=binding.FP64, cooling=cool, grav_G=gG, ionisation=ion)
+    if legs:
+        ref = binding.Box(shape, precision=binding.FP64, **phys)
+        ref.init_state(W)
+        for _ in range(args.warmup):
+            ref.step(ref.cfl_dt())
         ref.init_state(W)
         el64, ref_dts = _timed_run(ref, steps, record=True)
         t64 = ref.totals()
         G64 = ref.get_state()
-        absq = np.abs(G64).reshape(binding.NFIELDS, -1).sum(axis=1)
-        del G64
-        extra["fp64_same_seed"] = {"value": round(ncell * steps / el64, 1), "ms_per_step": round(el64 / steps * 1e3, 3)}
+        ref.close()
         del ref
         torch.cuda.empty_cache()
-        box = binding.Box(shape, precision=cfg["precision"], cooling=cool, grav_G=gG, ionisation=ion)
-        box.init_state(W)
+        log("FP64 reference run: %d steps, %.3f s" % (steps, el64))
+        if args.config == "c3":
+            extra["fp64_same_seed"] = {"value": round(ncell * steps / el64, 1),
+                                       "ms_per_step": round(el64 / steps * 1e3, 3)}
 
-    _copy_calibration()
-    box.set_timing(True)
-    el, dts = _timed_run(box, steps, ref_dts)
-    timing = box.get_timing()
-    box.set_timing(False)
-    esz = 8 if cfg["precision"] == binding.FP64 else 4
-    out = {
-        "metric": METRIC, "value": round(ncell * steps / el, 1), "unit": "cell-updates/s",
-        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(el / steps * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": cfg["dtype"],
-        "data": "synthetic",
-        "config": {"workload": cfg["desc"], "cells": ncell, "grid": list(shape)[::-1], "cfl": 0.3,
-                   "gamma": 5.0 / 3.0, "theta": 1.0, "heating_cooling": cool, "self_gravity": gG > 0, "ionisation": ion,
-                   "parallelism": "single GPU"},
-        # counters are keyed by workload: self-gravity and the ionisation
-        # network change the face kernels, heating/cooling only the tail
-        "roofline": _roofline(timing, ncell, esz, args.config + ("+gravity" if gG > 0 else "") + ("+ionisation" if ion else "")),
-        "step_roofline": _step_roofline(ncell * steps / el, esz),
-        "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
-    }
-    tot = box.totals()
-    out["totals_end"] = [float(x) for x in tot]
     if args.config == "c3":
-        out["fp32_total_rel_err"] = {binding.FIELDS[f]: float(abs(tot[f] - t64[f]) / absq[f])
-                                     for f in range(binding.NFIELDS) if absq[f] > 0}
-        G32 = box.get_state()
+        leg = _precision_leg(W, shape, steps, args.warmup, ref_dts, G64, t64, phys, workload)
+        del G64
+        out = {
+            "metric": METRIC, "value": leg["value"], "unit": "cell-updates/s",
+            "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": leg["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": cfg["dtype"],
+            "data": "synthetic",
+            "config": {"workload": cfg["desc"], "cells": ncell, "grid": list(shape)[::-1], "cfl": 0.3,
+                       "gamma": 5.0 / 3.0, "theta": 1.0, "heating_cooling": cool, "self_gravity": gG > 0,
+                       "ionisation": ion, "parallelism": "single GPU"},
+        }
+        for k in ("roofline", "step_roofline", "kernel_ms_per_step", "gate_total_rel", "max_total_rel_err"):
+            out[k] = leg[k]
+        out["fp32_total_rel_err"] = leg["total_rel_err"]
+        out["fp32_field_err"] = leg["fp32_field_err"]
         out.update(extra)
-        del G32
+    else:
+        box = binding.Box(shape, precision=cfg["precision"], **phys)
+        box.init_state(W)
+        for _ in range(args.warmup):
+            box.step(box.cfl_dt())
+        box.init_state(W)      # timed run starts from the initial condition
+        _copy_calibration()
+        box.set_timing(True)
+        el, _ = _timed_run(box, steps)
+        timing = box.get_timing()
+        box.set_timing(False)
+        tot = box.totals()
+        box.close()
+        del box
+        torch.cuda.empty_cache()
+        log("timed run: %d steps, %.3f s" % (steps, el))
+        out = {
+            "metric": METRIC, "value": round(ncell * steps / el, 1), "unit": "cell-updates/s",
+            "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(el / steps * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": cfg["dtype"],
+            "data": "synthetic",
+            "config": {"workload": cfg["desc"], "cells": ncell, "grid": list(shape)[::-1], "cfl": 0.3,
+                       "gamma": 5.0 / 3.0, "theta": 1.0, "heating_cooling": cool, "self_gravity": gG > 0,
+                       "ionisation": ion, "parallelism": "single GPU"},
+            # counters are keyed by workload: self-gravity and the ionisation
+            # network change the face kernels, heating/cooling only the tail
+            "roofline": _roofline(timing, ncell, esz, workload),
+            "step_roofline": _step_roofline(ncell * steps / el, esz),
+            "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in timing.items()},
+            "totals_end": [float(x) for x in tot],
+        }
+        if legs:
+            # the timed run (device-resident dt) and the reference run (dt read
+            # back) compute the same bits
+            out["reference_run_bitwise"] = bool(np.array_equal(tot, t64))
+            out["fp32_leg"] = _precision_leg(W, shape, steps, args.warmup, ref_dts, G64, t64, phys, workload)
+            del G64
+            log("FP32 leg done")
+            out["serving_leg"] = _serving(args.requests, 50)
+            log("serving leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(cooling=cool, grav_G=gG, ionisation=ion)
     print(json.dumps(out), flush=True)

@@ -90,11 +90,13 @@ def turbulence(n, seed, mach, beta, x_h2, lognormal_sigma=None, rho0=1.0, p0=1.0
     """Supersonic MHD turbulence start: GRF velocity (k^-2, k = 1..8) at rms
     Mach ``mach``, mean field B0 = sqrt(2 p0 / beta) along x, isothermal
     pressure p = p0 rho / rho0, optional lognormal density of width sigma.
+    ``n``: cells per axis of a cube, or a shape (nz, ny, nx) (thin boxes keep
+    the wavenumbers their axes can hold).
     ``log``: optional callable given a progress string after each field."""
-    shape = (n, n, n)
+    shape = (n, n, n) if np.isscalar(n) else tuple(int(x) for x in n)
     rng = np.random.default_rng(seed)
     # boxes of 512^3 and more draw their random fields in single precision
-    dt = np.float32 if n >= 512 else np.float64
+    dt = np.float32 if int(np.prod(shape)) >= 512 ** 3 else np.float64
     W = _alloc(shape)
     if lognormal_sigma is None:
         W[0] = rho0

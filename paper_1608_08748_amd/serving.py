@@ -11,9 +11,11 @@ import numpy as np
 
 def run(server, states, steps, arrivals=None, keep_state=False, borrow=False):
     """states: list of primitive arrays; arrivals: seconds after start for each
-    request (None = all at t = 0); borrow: lend the arrays to the server
-    instead of copying them at submission.  Returns a dict of per-request
-    records and aggregate statistics."""
+    request (None = all at t = 0); keep_state: True for every request, or a
+    collection of request indices whose final state the server keeps for
+    ``server.result``; borrow: lend the arrays to the server instead of
+    copying them at submission.  Returns a dict of per-request records and
+    aggregate statistics."""
     nreq = len(states)
     arr = np.zeros(nreq) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
     order = np.argsort(arr, kind="stable")
@@ -27,7 +29,8 @@ def run(server, states, steps, arrivals=None, keep_state=False, borrow=False):
         now = time.perf_counter() - t0
         while nxt < nreq and arr[order[nxt]] <= now:
             i = int(order[nxt])
-            sid = server.submit(states[i], steps, keep_state=keep_state, borrow=borrow)
+            keep = keep_state if isinstance(keep_state, bool) else i in keep_state
+            sid = server.submit(states[i], steps, keep_state=keep, borrow=borrow)
             sid_of[sid] = i
             nxt += 1
         na, npend = server.progress()

@@ -2,7 +2,7 @@
 on the same seeded inputs, plus GPU-side invariants.
 
 Tolerances (FP64 path): per-field L1 difference <= 1e-12 of the field's L1
-norm (vector components: of the vector's L1 norm) and
+norm (a vector component that is zero to roundoff: of the vector's) and
 conserved totals relative to sum |q| <= 1e-12.  Both sides take the same
 limiter and Riemann decisions in FP64; the remaining differences are the
 rounding of differently ordered FP64 expressions (about 1e-16 per operation).
@@ -35,24 +35,31 @@ def rel_l1(a, b):
 
 
 def field_scale(U, f):
-    """L1 scale of field f: its own for scalars, the whole vector's for the
-    momentum and face-field components (a component that is identically zero,
-    e.g. m_z in a 2D problem, is compared against the vector's magnitude)."""
-    if 1 <= f <= 3:
-        return float(np.abs(U[1:4]).sum())
-    if 6 <= f <= 8:
-        return float(np.abs(U[6:9]).sum())
-    return float(np.abs(U[f]).sum())
+    """L1 scale of field f: its own L1 norm; a momentum or face-field
+    component whose own norm is at roundoff against its vector's (e.g. m_z
+    in a 2D problem, identically zero on both sides) is compared against the
+    vector's norm instead."""
+    own = float(np.abs(U[f]).sum())
+    if 1 <= f <= 3 or 6 <= f <= 8:
+        lo = 1 if f <= 3 else 6
+        vec = float(np.abs(U[lo:lo + 3]).sum())
+        if own <= 1e-12 * vec:
+            return vec
+    return own
 
 
 def assert_fields_close(G, U, tol, what=""):
+    """Per-field L1 difference relative to field_scale, gated at tol; the L1
+    and max-abs differences of every field are printed."""
     worst = []
+    rows = []
     for f in range(binding.NFIELDS):
-        e = float(np.abs(G[f] - U[f]).sum()) / max(field_scale(U, f), 1e-300)
+        d = np.abs(G[f] - U[f])
+        e = float(d.sum()) / max(field_scale(U, f), 1e-300)
         worst.append(e)
-        assert e <= tol, "%s field %s: L1 rel %.3e (max abs %.3e)" % (what, binding.FIELDS[f], e,
-                                                                      np.abs(G[f] - U[f]).max())
-    print("%s worst L1 rel %.2e" % (what, max(worst)), flush=True)
+        rows.append("%s %.1e/%.1e" % (binding.FIELDS[f], e, float(d.max())))
+        assert e <= tol, "%s field %s: L1 rel %.3e (max abs %.3e)" % (what, binding.FIELDS[f], e, d.max())
+    print("%s worst L1 rel %.2e; per field L1 rel / max abs: %s" % (what, max(worst), ", ".join(rows)), flush=True)
 
 
 def _pair(W, **kw):
@@ -278,11 +285,16 @@ def test_fp32_mixed_against_fp64(recipe):
     A, B = a.get_state(), b.get_state()
     ta, tb = a.totals(), b.totals()
     absq = np.abs(A).reshape(binding.NFIELDS, -1).sum(axis=1)
-    for f in (0, 1, 2, 3, 4, 6, 7, 8):
+    # every total, e and rho_H2 included (H+ is zero without the network)
+    for f in range(binding.NFIELDS - 1):
         assert abs(ta[f] - tb[f]) <= 1e-5 * absq[f], (binding.FIELDS[f], abs(ta[f] - tb[f]) / absq[f])
-    errs = [rel_l1(B[f], A[f]) for f in range(binding.NFIELDS)]
-    print("fp32 field L1 rel", ["%.1e" % e for e in errs], flush=True)
-    assert max(errs[:9]) < 1e-3
+    errs = [rel_l1(B[f], A[f]) for f in range(binding.NFIELDS - 1)]
+    linf = [float(np.abs(B[f] - A[f]).max() / max(np.abs(A[f]).max(), 1e-300)) for f in range(binding.NFIELDS - 1)]
+    print("fp32 vs fp64 after 10 steps, field L1 / Linf rel",
+          ["%s %.1e/%.1e" % (binding.FIELDS[f], errs[f], linf[f]) for f in range(binding.NFIELDS - 1)], flush=True)
+    # fields are reported, not gated at the totals' bar: rounding differences
+    # grow in supersonic turbulence; this bound only catches a broken kernel
+    assert max(errs) < 1e-3
 
 
 @pytest.mark.slow

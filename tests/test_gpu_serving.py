@@ -154,3 +154,31 @@ def test_progress_reports_each_request_once():
     sv.close()
     assert sorted(seen) == sorted(ids)
     assert (na, npend) == (0, 0)
+
+
+def test_served_fp64_boxes_match_oracle():
+    # boxes of three sizes served together in FP64 (each at its own device
+    # CFL step) against the oracle run on each box alone at its CFL steps:
+    # fields L1 and totals at the FP64 bar
+    import oracle
+    states = [inputs.turbulence(16, seed=61, mach=3.0, beta=1.0, x_h2=1e-3),
+              inputs.turbulence(24, seed=62, mach=6.0, beta=0.3, x_h2=1e-2),
+              inputs.white_noise((8, 12, 20), seed=63, sigma=0.3, B=(0.2, 0.1, 0.0))]
+    steps = 3
+    mix, res = _serve(states, binding.FP64, steps=steps)
+    assert mix["max_active"] == 3
+    for W, G, rec in zip(states, res, mix["records"]):
+        P = oracle.make_params(W.shape[1:])
+        U = oracle.prim_to_cons(P, W)
+        for _ in range(steps):
+            oracle.step(P, U, oracle.cfl_dt(P, U))
+        worst = 0.0
+        for f in range(binding.NFIELDS):
+            scale = np.abs(U[f]).sum()
+            e = np.abs(G[f] - U[f]).sum() / scale if scale > 0 else np.abs(G[f]).sum()
+            worst = max(worst, e)
+            assert e <= 1e-12, (W.shape, binding.FIELDS[f], e)
+        to = oracle.totals(P, U)
+        absq = np.abs(U).reshape(binding.NFIELDS, -1).sum(axis=1)
+        assert np.all(np.abs(np.asarray(rec["totals"]) - to) <= 1e-12 * absq)
+        print("served box %s vs oracle: worst field L1 rel %.1e" % (W.shape[1:], worst), flush=True)

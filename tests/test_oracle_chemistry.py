@@ -8,6 +8,7 @@
   to C / D as tau -> infinity, and stays within [0, all hydrogen molecular].
 """
 import numpy as np
+import pytest
 
 import oracle
 
@@ -108,3 +109,100 @@ def test_chemistry_changes_only_h2():
     oracle.chemistry(P, V, 1e-3)
     np.testing.assert_array_equal(V[:9], U[:9])
     assert not np.array_equal(V[9], U[9])
+
+
+# ---- composition of C and D (Sec. 2.7 with reactions 1-4 of the rate appendix)
+#
+# The rates k1'..k4 are pinned above; these tests pin how the step combines
+# them with the species densities: n_H = n_u (rho - rho_H2), n_H2 = n_u rho_H2
+# / 2, C = k1' n n_H (k1 carries the printed n / n_H factor), D = k2 n_H + k3
+# n_H2 + k4, then one semi-implicit update.  The expected new density is
+# composed here from the species densities of the chosen state and checked
+# against the returned density (not against the oracle's own C and D), at
+# one temperature in each combination of the k2 / k3 branches; each case
+# also checks that a swap of k2 and k3, or of n_H and n_H2, would move the
+# result far beyond the tolerance.
+
+def _e_for_T(P, rho, h2, T, hp=0.0, gam=None):
+    # T = T_u mu p / rho with p = (gamma - 1) e and mu = 1 / (1 - x_H2 / 2 + x_H+)
+    mu = 1.0 / (1.0 - 0.5 * h2 / rho + hp / rho)
+    g = P.gamma if gam is None else gam
+    return T * rho / (P.T_unit * mu * (g - 1.0))
+
+
+def _semi_implicit(n, C, D, ts):
+    return n + ts * (C - D * n) / (1.0 + ts * D)
+
+
+# (T, which branches): 5000 K both low; 7340 K k3 high, k2 low; 9000 K both high
+@pytest.mark.parametrize("T", [5000.0, 7340.0, 9000.0])
+def test_h2_update_composition(T):
+    P = _P()
+    rho, h2 = 2.0, 0.6
+    e = _e_for_T(P, rho, h2, T)
+    k1b, k2, k3, k4 = oracle.k_rates(T)
+    nH = P.n_unit * (rho - h2)
+    nH2 = P.n_unit * h2 / 2.0
+    n = nH + nH2
+    assert nH != nH2 and abs(k2 - k3) > 0.05 * max(k2, k3)
+    # a step with tau D of order one, so C and D both shape the result
+    D = k2 * nH + k3 * nH2 + k4
+    dt = 1.0 / (D * P.t_unit)
+    ts = dt * P.t_unit
+    want = 2.0 * _semi_implicit(nH2, k1b * n * nH, D, ts) / P.n_unit
+    got, r = oracle.chem_cell(P, rho, e, h2, dt)
+    assert abs(r["T"] - T) < 1e-9 * T
+    assert abs(got - want) <= 1e-12 * want
+    # the test discriminates: swapped rates or swapped species move the result
+    for Dx, Cx in ((k3 * nH + k2 * nH2 + k4, k1b * n * nH), (k2 * nH2 + k3 * nH + k4, k1b * n * nH2)):
+        other = 2.0 * _semi_implicit(nH2, Cx, Dx, ts) / P.n_unit
+        assert abs(other - want) > 1e-6 * want
+
+
+@pytest.mark.parametrize("T", [5000.0, 7340.0, 9000.0])
+def test_h2_and_hplus_update_composition_with_ions(T):
+    # reactions 1-8: n_H = n_u (rho - rho_H2 - rho_H+), n_e = n_H+ = n_u rho_H+,
+    # n = n_H + n_H2 + n_H+; H2 as above with the H+ clamp n_H2 <= n_u (rho -
+    # rho_H+) / 2; H+ with C = k5 n_H + k6 n_H n_e, D = (k7 + k8) n_e
+    P = oracle.make_params((1, 1, 1), ionisation=True)
+    rho, h2, hp = 2.0, 0.6, 0.3
+    nH = P.n_unit * (rho - h2 - hp)
+    nH2 = P.n_unit * h2 / 2.0
+    ne = P.n_unit * hp
+    gam = (5 * nH + 5 * ne + 7 * nH2) / (3 * nH + 3 * ne + 5 * nH2)
+    e = _e_for_T(P, rho, h2, T, hp=hp, gam=gam)
+    k1b, k2, k3, k4 = oracle.k_rates(T)
+    k5, k6, k7, k8 = oracle.ion_rates(T)
+    n = nH + nH2 + ne
+    D = k2 * nH + k3 * nH2 + k4
+    dt = 1.0 / (D * P.t_unit)
+    ts = dt * P.t_unit
+    m2 = min(_semi_implicit(nH2, k1b * n * nH, D, ts), P.n_unit * (rho - hp) / 2.0)
+    h2_want = 2.0 * m2 / P.n_unit
+    mi = _semi_implicit(ne, k5 * nH + k6 * nH * ne, (k7 + k8) * ne, ts)
+    mi = min(max(mi, 0.0), P.n_unit * (rho - h2_want))
+    hp_want = mi / P.n_unit
+    h2n, hpn, r = oracle.chem_cell_ion(P, rho, e, h2, hp, dt)
+    assert abs(r["T"] - T) < 1e-9 * T
+    assert abs(h2n - h2_want) <= 1e-12 * h2_want
+    assert abs(hpn - hp_want) <= 1e-12 * hp_want
+    for Dx, Cx in ((k3 * nH + k2 * nH2 + k4, k1b * n * nH), (k2 * nH2 + k3 * nH + k4, k1b * n * nH2)):
+        other = 2.0 * _semi_implicit(nH2, Cx, Dx, ts) / P.n_unit
+        assert abs(other - h2_want) > 1e-6 * h2_want
+
+
+def test_ion_network_without_ions_reduces_to_h2_network():
+    # with no H+ the H2 half of the eight-reaction update is the four-reaction
+    # update at the cell's gamma_eff (two separately written oracle functions)
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        rho = rng.uniform(0.2, 5.0)
+        h2 = rho * rng.uniform(0.0, 0.9)
+        e = rng.uniform(0.1, 10.0)
+        dt = 10 ** rng.uniform(-5, -1)
+        Pi = oracle.make_params((1, 1, 1), ionisation=True)
+        gam = oracle.gamma_cell(Pi, rho, h2, 0.0)
+        Pg = oracle.make_params((1, 1, 1), gamma=gam)
+        h2i, hpi, _ = oracle.chem_cell_ion(Pi, rho, e, h2, 0.0, dt)
+        h2g, _ = oracle.chem_cell(Pg, rho, e, h2, dt)
+        assert abs(h2i - h2g) <= 1e-13 * max(h2g, 1e-300)

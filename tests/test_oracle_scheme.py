@@ -209,3 +209,46 @@ def test_low_beta_without_sync_is_stable():
         oracle.adv_stage(P, U, dt)
     p = (P.gamma - 1.0) * U[5]
     assert np.abs(p - 0.1).max() < 1e-6
+
+
+# ---- regularisation (Sec. 2.8, dual-energy sync) on hand-built single cells
+#
+# A 1x1x1 periodic box: both faces of each field component are the same
+# stored value, so the cell-centre field is that value.  K = m^2 / (2 rho),
+# M = B^2 / 2; e := E - K - M exactly where E - K - M >= 1e-3 E and
+# (gamma - 1)(E - K - M) > M, else e is kept.  Every value below is exact in
+# binary, so each expectation is exact.
+
+def _one_cell(rho, m, E, e, b, gamma=5.0 / 3.0):
+    P = oracle.make_params((1, 1, 1), gamma=gamma)
+    U = np.zeros((oracle.NF, 1, 1, 1))
+    U[0] = rho
+    U[1:4, 0, 0, 0] = m
+    U[4] = E
+    U[5] = e
+    U[6:9, 0, 0, 0] = b
+    return P, U
+
+
+@pytest.mark.parametrize("case", [
+    # (rho, m, E, e, B, gamma, expected e): sync, K = 0.5, M = 0.5, E - K - M = 2
+    (1.0, (1.0, 0, 0), 3.0, 1.75, (1.0, 0, 0), 5.0 / 3.0, 2.0),
+    # kept by the 1e-3 gate: K = 0.5, M = 0, E - K - M = 2^-11 < 1e-3 E
+    (1.0, (1.0, 0, 0), 0.5 + 2.0 ** -11, 0.25, (0, 0, 0), 5.0 / 3.0, 0.25),
+    # just inside the 1e-3 gate: E - K - M = 2^-10 >= 1e-3 E (pressure gate open, M = 0)
+    (1.0, (1.0, 0, 0), 0.5 + 2.0 ** -10, 0.25, (0, 0, 0), 5.0 / 3.0, 2.0 ** -10),
+    # kept by the pressure gate: M = 2, E - K - M = 1, (gamma - 1) 1 = 2/3 < 2
+    (1.0, (0, 0, 0), 3.0, 0.5, (2.0, 0, 0), 5.0 / 3.0, 0.5),
+    # B = (1, 1, 1): M = 1.5, E - K - M = 1; with gamma = 3, (gamma - 1) 1 = 2 > M -> sync
+    (1.0, (0, 0, 0), 2.5, 0.5, (1.0, 1.0, 1.0), 3.0, 1.0),
+    # the same cell at gamma = 5/3: (2/3) 1 < M -> kept
+    (1.0, (0, 0, 0), 2.5, 0.5, (1.0, 1.0, 1.0), 5.0 / 3.0, 0.5),
+])
+def test_regularisation_branches(case):
+    rho, m, E, e, b, gamma, want = case
+    P, U = _one_cell(rho, m, E, e, b, gamma)
+    before = U.copy()
+    oracle.regularise(P, U)
+    assert U[5, 0, 0, 0] == want
+    # only e may change
+    np.testing.assert_array_equal(np.delete(U, 5, axis=0), np.delete(before, 5, axis=0))
