@@ -57,7 +57,9 @@ enum {
     MHD_ENOMEM = -2,     /* workspace missing or smaller than mhd_workspace_bytes */
     MHD_EDEVICE = -3,    /* a HIP runtime call failed                             */
     MHD_ECFL = -4,       /* a step used dt above the CFL bound of its start state */
-    MHD_ENONPHYS = -5    /* non-finite or non-positive rho or e after a step       */
+    MHD_ENONPHYS = -5,   /* non-finite or non-positive rho or e after a step       */
+    MHD_ETOOLARGE = -6   /* box beyond the static scratch of an allocation-free    */
+                         /* entry point (MHD_NOALLOC_MAX_CELLS)                    */
 };
 
 enum { MHD_FP64 = 0, MHD_FP32_MIXED = 1 };
@@ -169,6 +171,35 @@ int mhd_step_cfl(mhd_box *b);
  * the face fields sum their face values).  Fixed-order tree reduction:
  * repeatable bit for bit.  Synchronises; returns a latched fault if any. */
 int mhd_conserved_totals(mhd_box *b, double out[MHD_NFIELDS]);
+
+/* For callers that cannot allocate device memory or bind a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the FP64 totals of mhd_conserved_totals (same kernels, same
+ * fixed-order tree, so the same bits for the same stored values) of a state
+ * held in the caller's own device memory.  Allocates nothing: the per-block
+ * partial sums live in a static device array of the library (5.5 MiB per
+ * device, held until the process ends).
+ *   state      device pointer: MHD_NFIELDS fields of n[0]*n[1]*n[2] values,
+ *              field order and layout of the box state (structure of arrays,
+ *              x fastest), double for MHD_FP64, float for MHD_FP32_MIXED;
+ *              only read
+ *   precision  MHD_FP64 or MHD_FP32_MIXED
+ *   n          cells along x, y, z; n[0]*n[1]*n[2] <= MHD_NOALLOC_MAX_CELLS
+ *              (else MHD_ETOOLARGE, nothing launched)
+ *   stream     hipStream_t of the current device; NULL = the null stream
+ *   out        device pointer to MHD_NFIELDS doubles, written by the last
+ *              kernel
+ * Runs on the current device; asynchronous on stream (no synchronisation,
+ * no host copy), so it can be captured.  Every call on one device shares
+ * that device's partial-sum array: calls that overlap in time on one device
+ * (on different streams or from different threads) race; calls ordered on
+ * one stream do not.  Every partial is written before it is read, so no call
+ * depends on what an earlier call left there.  The first call on a device
+ * looks the array's device address up (hipGetSymbolAddress); MHD_EDEVICE if
+ * that or a launch fails. */
+enum { MHD_NOALLOC_MAX_CELLS = 16777216 };   /* 256^3 */
+int mhd_conserved_totals_noalloc(const void *state, int32_t precision, const int32_t n[3], void *stream,
+                                 double *out);
 
 /* Run one part of the step on the current state (stage selectors above),
  * for per-stage parity checks.  Asynchronous. */

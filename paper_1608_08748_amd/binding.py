@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmhdchem.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mhdchem.h")
 
-MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ECFL, MHD_ENONPHYS = 0, -1, -2, -3, -4, -5
+MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ECFL, MHD_ENONPHYS, MHD_ETOOLARGE = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_MAX_CELLS = 16777216   # MHD_NOALLOC_MAX_CELLS
 FP64, FP32_MIXED = 0, 1
 STAGE_NONADV, STAGE_ADV, STAGE_TAIL, STAGE_NONADV_RHS, STAGE_ADV_RHS = 1, 2, 3, 4, 5
 FIELDS = ("rho", "mx", "my", "mz", "E", "e", "bx", "by", "bz", "h2", "hp")
@@ -124,6 +125,8 @@ def lib():
         "mhd_step": ([B, ctypes.c_double], ctypes.c_int),
         "mhd_step_cfl": ([B], ctypes.c_int),
         "mhd_conserved_totals": ([B, _D], ctypes.c_int),
+        "mhd_conserved_totals_noalloc": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
         "mhd_debug_stage": ([B, ctypes.c_int, ctypes.c_double], ctypes.c_int),
         "mhd_destroy": ([B], ctypes.c_int),
         "mhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -279,6 +282,22 @@ class Box:
             self.close()
         except Exception:
             pass
+
+
+def conserved_totals_noalloc(state, precision, out, stream=None):
+    """mhd_conserved_totals_noalloc on device tensors: state (MHD_NFIELDS, nz,
+    ny, nx), float64 for FP64 or float32 for FP32_MIXED, contiguous; out: 11
+    float64 on the same device.  Asynchronous on the stream (default: the
+    current one)."""
+    import torch
+    assert state.is_cuda and out.is_cuda and state.is_contiguous() and out.is_contiguous()
+    assert state.dim() == 4 and state.shape[0] == NFIELDS and out.dtype == torch.float64 and out.numel() >= NFIELDS
+    assert state.dtype == (torch.float64 if precision == FP64 else torch.float32)
+    nz, ny, nx = state.shape[1:]
+    n = (ctypes.c_int32 * 3)(nx, ny, nz)
+    s = stream if stream is not None else torch.cuda.current_stream(state.device)
+    return lib().mhd_conserved_totals_noalloc(ctypes.c_void_p(state.data_ptr()), int(precision), n,
+                                              ctypes.c_void_p(s.cuda_stream), ctypes.c_void_p(out.data_ptr()))
 
 
 def server_params(precision=FP32_MIXED, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None,

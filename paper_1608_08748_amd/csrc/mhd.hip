@@ -25,6 +25,7 @@
 #include <cstdint>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -1162,6 +1163,59 @@ int server_progress(mhd_server* sv, int* nact, int* npend)
 
 // ---------------------------------------------------------------- C ABI
 
+// ---------------------------------------------------------------- allocation-free totals
+
+// Per-block partial sums of mhd_conserved_totals_noalloc: NF doubles for each
+// 256-cell block of a box of at most MHD_NOALLOC_MAX_CELLS cells (5.5 MiB).
+// Each device that loads the library holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returned for the current device.
+constexpr size_t NOALLOC_BLOCKS = ((size_t)MHD_NOALLOC_MAX_CELLS + NTH - 1) / NTH;
+static __device__ __align__(256) double scratch[NOALLOC_BLOCKS * NF];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// device address of this device's scratch array, looked up once per device
+// with that device current
+int scratch_of_current_device(double** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return MHD_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MHD_EDEVICE;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MHD_OK;
+}
+
+template <typename T>
+int totals_noalloc(const void* state, const Geo& g, hipStream_t s, double* part, double* out)
+{
+    typename BTotalsPartial<T>::Args pa;
+    pa.g = g;
+    const T* base = static_cast<const T*>(state);
+    for (int f = 0; f < NF; f++) pa.U.f[f] = base + (size_t)f * (size_t)g.n;
+    pa.part = part;
+    const int nblocks = (g.n + NTH - 1) / NTH;
+    k_one<BTotalsPartial<T>><<<nblocks, NTH, 0, s>>>(pa);
+    BTotalsFinal::Args fa;
+    fa.part = part;
+    fa.nparts = nblocks;
+    fa.out = out;
+    k_one<BTotalsFinal><<<1, BTotalsFinal::NT, 0, s>>>(fa);
+    return launch_status();
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t mhd_workspace_bytes(const mhd_params* p)
@@ -1278,6 +1332,27 @@ int mhd_conserved_totals(mhd_box* b, double out[MHD_NFIELDS])
     return b->prec == MHD_FP64 ? totals<double>(b, out) : totals<float>(b, out);
 }
 
+int mhd_conserved_totals_noalloc(const void* state, int32_t precision, const int32_t n[3], void* stream,
+                                 double* out)
+{
+    if (!state || !n || !out || (precision != MHD_FP64 && precision != MHD_FP32_MIXED)) return MHD_EINVAL;
+    if (!valid_dims(n)) return MHD_EINVAL;
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    if (cells > MHD_NOALLOC_MAX_CELLS) return MHD_ETOOLARGE;
+    double* part = nullptr;
+    int st = scratch_of_current_device(&part);
+    if (st) return st;
+    Geo g;
+    g.nx = n[0];
+    g.ny = n[1];
+    g.nz = n[2];
+    g.nxy = n[0] * n[1];
+    g.n = (int)cells;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return precision == MHD_FP64 ? totals_noalloc<double>(state, g, s, part, out)
+                                 : totals_noalloc<float>(state, g, s, part, out);
+}
+
 int mhd_debug_stage(mhd_box* b, int stage, double dt)
 {
     if (!b) return MHD_EINVAL;
@@ -1303,6 +1378,7 @@ const char* mhd_strerror(int status)
     case MHD_EDEVICE: return "HIP runtime error";
     case MHD_ECFL: return "time step above the CFL bound";
     case MHD_ENONPHYS: return "non-finite or non-positive density or internal energy";
+    case MHD_ETOOLARGE: return "box larger than the static scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
