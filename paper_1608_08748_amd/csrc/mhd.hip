@@ -394,6 +394,26 @@ int ztile_blocks(const Geo& g, const ZTile& z)
     return z.ntx * z.nty * ((g.nz + z.seg - 1) / z.seg);
 }
 
+// the ADV update forms the x faces itself when whole x rows fit its block
+constexpr int XZ_MAXT = 256;
+
+bool adv_xz(const Geo& g) { return g.nx <= XZ_MAXT; }
+
+// rows per block, row groups and z segment of the fused ADV update
+void xz_tiling(const Geo& g, int& rpb, int& nrg, int& seg)
+{
+    rpb = XZ_MAXT / g.nx;
+    nrg = (g.ny + rpb - 1) / rpb;
+    seg = g.nz < ZMARCH_SEG ? g.nz : ZMARCH_SEG;
+}
+
+int xz_blocks(const Geo& g)
+{
+    int rpb, nrg, seg;
+    xz_tiling(g, rpb, nrg, seg);
+    return nrg * ((g.nz + seg - 1) / seg);
+}
+
 // One NONADV substage.  y and z faces first (marching kernels); then, for
 // boxes whose x rows fit a block, the x-row face kernel, which also updates
 // m, E and e, and the face-field update; otherwise the one-face-per-thread x
@@ -532,11 +552,31 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     Fields<T> in = view<T>(b, sin.h, sin.m, sin.b);
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
-    // x faces from staged row segments, one face per thread (an LDS row
-    // scheme that computes each cell's slopes once measured slower: block
-    // barriers, fewer waves); y faces marched along y, each cell's parabola
-    // formed once
-    if (b->p.ionisation) {
+    const bool ion = b->p.ionisation != 0;
+    if (adv_xz(b->g)) {
+        // y faces marched along y; the x faces inside the z-marching update
+        if (ion) emit_adv_face<T, 1, 8>(b, e, in, a);
+        else emit_adv_face<T, 1, 7>(b, e, in, a);
+        AdvXZArgs<T> xa;
+        xa.g = b->g;
+        xa.U = cview(in);
+        xa.S = cview(S);
+        xa.O = out;
+        xa.Fy = reinterpret_cast<T*>(b->F[1]);
+        xa.a = a;
+        xa.rk = rk;
+        xa.dbg = dbg;
+        xz_tiling(b->g, xa.rpb, xa.nrg, xa.seg);
+        const int blocks = xz_blocks(b->g);
+        auto shm = [](int nv, int nq) { return (size_t)2 * (nv + nq) * XZ_MAXT * sizeof(T); };
+        e.template launch<BAdvXZUpdate<T, 0, 4, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(4, 4), xa);   // rho, m
+        if (ion) e.template launch<BAdvXZUpdate<T, 4, 4, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(6, 4), xa);
+        else e.template launch<BAdvXZUpdate<T, 4, 3, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(5, 3), xa);
+        return;
+    }
+    // x faces from staged row segments, one face per thread; y faces marched
+    // along y, each cell's parabola formed once
+    if (ion) {
         emit_adv_face<T, 0, 8>(b, e, in, a);
         emit_adv_face<T, 1, 8>(b, e, in, a);
     } else {
@@ -719,9 +759,17 @@ void emit_step(mhd_box* b, Emit& e, const StepArgs& a)
 {
     if (b->grav) emit_poisson<T>(b, e);
     emit_nonadv_stage<T>(b, e, a, true);
-    // the tail of the step runs inside the last ADV launch
-    emit_adv_stage<T>(b, e, a, true);
-    emit_reduce_dt(b, e, ztile_blocks(b->g, ztile_of(b->g, NTH)));
+    if (adv_xz(b->g)) {
+        // the fused ADV update forms x faces at every plane; with the tail's
+        // FP64 chemistry on top it would spill, so the tail is a pass of its
+        // own (the same arithmetic)
+        emit_adv_stage<T>(b, e, a, false);
+        emit_tail<T>(b, e, a, 1);
+    } else {
+        // the tail of the step runs inside the last ADV launch
+        emit_adv_stage<T>(b, e, a, true);
+        emit_reduce_dt(b, e, ztile_blocks(b->g, ztile_of(b->g, NTH)));
+    }
 }
 
 // ---------------------------------------------------------------- single-box operations

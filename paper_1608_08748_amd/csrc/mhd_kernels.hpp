@@ -1498,6 +1498,236 @@ struct BAdvZUpdate {
     }
 };
 
+// ADV update with the x faces formed in the same kernel (boxes whose x rows
+// fit a block).  A block holds rpb whole x rows (nx <= NT), one thread per
+// column, and marches its rows along z over a segment of cells, like
+// BAdvZUpdate (z faces from the sliding window, y fluxes from memory, the
+// Runge-Kutta update; the tail of the step follows as a pass of its own).  At each plane the threads publish
+// their cell's values in LDS and form the flux of their lower x face exactly
+// as BAdvFaceXRow does (sqrt(rho)-weighted velocity, the upwind cell's
+// parabola from its 5-cell window at fixed row offsets, periodic inside the
+// row); the fluxes are exchanged through LDS for the x difference, so the x
+// fluxes never pass through memory.  Two block barriers per plane; the LDS is
+// double-buffered by plane parity, so a buffer is rewritten only after every
+// thread has passed the barriers that follow its last reads.  Dynamic LDS:
+// 2 x (NV + NQ) x NT values.  Threads beyond the block's rows (and the rows
+// of a last, partial row group) reach every barrier: they read row 0 of the
+// block, which is always a real row, and write nothing, to LDS or memory.
+template <typename T>
+struct AdvXZArgs {
+    Geo g;
+    CFields<T> U, S;
+    Fields<T> O;
+    const T* Fy;
+    StepArgs a;
+    RK rk;
+    int dbg;
+    int rpb;    // x rows per block (nx * rpb <= NT)
+    int nrg;    // row groups: ceil(ny / rpb)
+    int seg;    // z cells per block
+};
+
+template <typename T, int Q0, int NQ, int MAXT>
+struct BAdvXZUpdate {
+    static constexpr int NT = MAXT;
+    static constexpr bool XCD = false;
+    // rho and m of the cell are window fields 0-3 of the first group;
+    // the energy group stages rho and mx of the cell as two more values
+    static constexpr bool own_v = Q0 == 0 && NQ >= 4;
+    static constexpr int NV = own_v ? NQ : NQ + 2;
+    static constexpr int RI = own_v ? 0 : NQ;       // staged slot of rho
+    static constexpr int MXI = own_v ? 1 : NQ + 1;  // staged slot of mx
+    using Args = AdvXZArgs<T>;
+    static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
+    {
+        extern __shared__ unsigned char smem_raw[];
+        T* sm = reinterpret_cast<T*>(smem_raw);
+        const Geo& g = A.g;
+        const int nx = g.nx;
+        const int r = tid / nx;
+        const int i = tid - r * nx;
+        const int rg = blk % A.nrg, sgi = blk / A.nrg;
+        const int j0 = rg * A.rpb + r;
+        const bool act = r < A.rpb && j0 < g.ny;
+        // threads beyond the rows follow a column of row 0 of the block
+        const int rr = act ? r : 0;
+        const int j = act ? j0 : rg * A.rpb;
+        const int k0 = sgi * A.seg, k1 = min(k0 + A.seg, g.nz);
+        // threads of cells i-3 .. i+2 of the row
+        int tx[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) tx[m] = rr * nx + wrapc(i + m - 3, nx);
+        const int tme = rr * nx + i;
+        march(A, sm, act, i, j, k0, k1, tx, tme);
+    }
+    static __device__ __forceinline__ void march(const Args& A, T* sm, bool act, int i, int j, int x0, int x1,
+                                                 const int tx[6], int tme)
+    {
+        const Geo& g = A.g;
+        const int nd = g.nz;
+        const size_t N = (size_t)g.n;
+        const int base = i + g.nx * j;
+        const int stride = g.nxy;
+        const T ydx = T(A.a.theta * (step_dt(A.a) / A.a.h));
+        const T dtdx = T(step_dt(A.a) / A.a.h);
+        const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
+        const T ra = T(A.rk.a), rb = T(A.rk.b);
+        const int jp = j + 1 == g.ny ? 0 : j + 1;
+
+        // window cells z = x0-3 .. x0+2 (slots 0..5); vr, vm: rho and mz of
+        // slots 2 and 3 (z-face velocity); vx: mx of slots 2 and 3 (the
+        // energy group's x-face velocity; the first group holds it in w)
+        T w[NQ][6];
+        T vr[2], vm[2], vx[2] = { T(0), T(0) };
+#pragma unroll
+        for (int m = 0; m < 6; m++) {
+            int cc = base + wrapc(x0 - 3 + m, nd) * stride;
+#pragma unroll
+            for (int q = 0; q < NQ; q++) w[q][m] = A.U.f[fld[Q0 + q]][cc];
+            if (m == 2 || m == 3) {
+                vr[m - 2] = A.U.f[RHO][cc];
+                vm[m - 2] = A.U.f[MZ][cc];
+                if (!own_v) vx[m - 2] = A.U.f[MX][cc];
+            }
+        }
+        auto velocity = [&]() {
+            T rsl = rsqrt_nr(vr[0]), rsr = rsqrt_nr(vr[1]);
+            return (vm[0] * rsl + vm[1] * rsr) * rcp_nr(vr[0] * rsl + vr[1] * rsr);
+        };
+        // the first z face (slots 2, 3), as BAdvZUpdate
+        T Flo[NQ], pR[NQ], pdq[NQ], p6[NQ], d1[NQ], f1[NQ];
+        {
+            const T vf = velocity();
+            const bool upw = vf >= T(0);
+            const T y = upw ? ydx * vf : ydx * (-vf);
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                T s0 = limited_slope(w[q][0], w[q][1], w[q][2]);
+                T s1 = limited_slope(w[q][1], w[q][2], w[q][3]);
+                T s2 = limited_slope(w[q][2], w[q][3], w[q][4]);
+                T s3 = limited_slope(w[q][3], w[q][4], w[q][5]);
+                T i0 = interface_value(w[q][1], w[q][2], s0, s1);
+                T i1 = interface_value(w[q][2], w[q][3], s1, s2);
+                T i2 = interface_value(w[q][3], w[q][4], s2, s3);
+                Par<T> Pl = parabola_finish(w[q][0], w[q][1], w[q][2], w[q][3], w[q][4], i0, i1, s1);
+                Par<T> Pr = parabola_finish(w[q][1], w[q][2], w[q][3], w[q][4], w[q][5], i1, i2, s2);
+                T qup = upw ? avg_right(Pl, y) : avg_left(Pr, y);
+                Flo[q] = vf * qup;
+                pR[q] = Pr.qR;
+                pdq[q] = Pr.dq;
+                p6[q] = Pr.q6;
+                d1[q] = s3;
+                f1[q] = i2;
+            }
+        }
+        T nw[NQ], nvr = T(0), nvm = T(0), nvx = T(0);
+        auto fetch = [&](int x) {
+            int cn = base + wrapc(x + 3, nd) * stride;
+#pragma unroll
+            for (int q = 0; q < NQ; q++) nw[q] = A.U.f[fld[Q0 + q]][cn];
+            if (!own_v) {
+                int c1 = base + wrapc(x + 1, nd) * stride;
+                nvr = A.U.f[RHO][c1];
+                nvm = A.U.f[MZ][c1];
+                nvx = A.U.f[MX][c1];
+            }
+        };
+        fetch(x0);
+        for (int x = x0; x < x1; x++) {
+            // slide: window slots 0..5 = cells x-2 .. x+3
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+#pragma unroll
+                for (int m = 0; m < 5; m++) w[q][m] = w[q][m + 1];
+                w[q][5] = nw[q];
+            }
+            vr[0] = vr[1];
+            vm[0] = vm[1];
+            vx[0] = vx[1];
+            if constexpr (own_v) {
+                vr[1] = w[0][3];
+                vm[1] = w[3][3];
+            } else {
+                vr[1] = nvr;
+                vm[1] = nvm;
+                vx[1] = nvx;
+            }
+            if (x + 1 < x1) fetch(x + 1);
+            // the cell's y flux difference and Runge-Kutta input, loaded
+            // before any store
+            const int c = base + x * stride;
+            const int cyp = c + (jp - j) * g.nx;
+            T dy[NQ], sv[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                const size_t o = (size_t)(Q0 + q) * N;
+                dy[q] = A.Fy[o + cyp] - A.Fy[o + c];
+                sv[q] = A.S.f[fld[Q0 + q]][c];
+            }
+            // x faces of plane x: publish the cell, form the flux of its
+            // lower x face, exchange the fluxes
+            T* vb = sm + (x & 1) * ((NV + NQ) * NT);
+            T* fb = vb + NV * NT;
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < NQ; q++) vb[q * NT + tme] = w[q][2];
+                if constexpr (!own_v) {
+                    vb[RI * NT + tme] = vr[0];
+                    vb[MXI * NT + tme] = vx[0];
+                }
+            }
+            __syncthreads();
+            T fx[NQ];
+            {
+                // sqrt(rho)-weighted face velocity; sqrt(rho) v = m / sqrt(rho)
+                const T rl = vb[RI * NT + tx[2]], rr = vb[RI * NT + tme];
+                const T rsl = rsqrt_nr(rl), rsr = rsqrt_nr(rr);
+                const T vf = (vb[MXI * NT + tx[2]] * rsl + vb[MXI * NT + tme] * rsr) * rcp_nr(rl * rsl + rr * rsr);
+                const bool upw = vf >= T(0);
+                const T y = upw ? ydx * vf : ydx * (-vf);
+                // the upwind cell's window: cells i-3 .. i+1 or i-2 .. i+2
+                int ix[5];
+#pragma unroll
+                for (int m = 0; m < 5; m++) ix[m] = upw ? tx[m] : tx[m + 1];
+#pragma unroll
+                for (int q = 0; q < NQ; q++) {
+                    const T* u = vb + q * NT;
+                    Par<T> P = parabola(u[ix[0]], u[ix[1]], u[ix[2]], u[ix[3]], u[ix[4]]);
+                    T qup = upw ? avg_right(P, y) : avg_left(P, y);
+                    fx[q] = vf * qup;
+                    if (act) fb[q * NT + tme] = fx[q];
+                }
+            }
+            __syncthreads();
+            // upper face of cell x along z: between slots 2 and 3
+            T Fup[NQ], nv[NQ];
+            BAdvZUpdate<T, Q0, NQ>::zflux(w, velocity(), ydx, pR, pdq, p6, d1, f1, Fup);
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                T dx = fb[q * NT + tx[4]] - fx[q];
+                T dz = Fup[q] - Flo[q];
+                T inc = -dtdx * ((dx + dy[q]) + dz);
+                if (A.dbg) {
+                    nv[q] = inc;
+                } else {
+                    T u = w[q][2];
+                    nv[q] = (u + ra * (sv[q] - u)) + rb * inc;
+                }
+                Flo[q] = Fup[q];
+            }
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < NQ; q++) A.O.f[fld[Q0 + q]][c] = nv[q];
+                if (Q0 == 0 && A.dbg) {
+                    A.O.f[BX][c] = T(0);
+                    A.O.f[BY][c] = T(0);
+                    A.O.f[BZ][c] = T(0);
+                }
+            }
+        }
+    }
+};
+
 // ---------------------------------------------------------------- tail and reductions
 
 // Tail of the step (after ADV) as a pass of its own: tail_cell on every cell,

@@ -619,16 +619,17 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+template <int NT = NTH>
 __device__ __forceinline__ void block_max_store(double v, double* out, int blk)
 {
-    __shared__ double red[NTH / 64];
+    __shared__ double red[NT / 64];
     v = wave_max(v);
     int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) red[wv] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = red[0];
-        for (int w = 1; w < NTH / 64; w++) m = red[w] > m ? red[w] : m;
+        for (int w = 1; w < NT / 64; w++) m = red[w] > m ? red[w] : m;
         out[blk] = m;
     }
 }

@@ -24,10 +24,11 @@ def _box(W):
     return box
 
 
-# launches per step and class: NONADV faces y, z, x-rows and the face-field
-# update per substage; ADV x faces and the y march, the two z-march update
-# launches per substage (the last one runs the tail); the CFL reduction
-PER_STEP = {"setup": 0, "nonadv_face": 9, "nonadv_update": 3, "adv_face": 6, "adv_update": 6, "tail": 0,
+# launches per step and class (x rows of at most 256 cells): NONADV faces y,
+# z, x-rows and the face-field update per substage; the ADV y march and the
+# two z-march update launches per substage, which form the x faces
+# themselves; the tail of the step; the CFL reduction
+PER_STEP = {"setup": 0, "nonadv_face": 9, "nonadv_update": 3, "adv_face": 3, "adv_update": 6, "tail": 1,
             "reduce": 1, "poisson": 0}
 
 
