@@ -130,7 +130,7 @@ bool valid_params(const mhd_params* p)
 // ionisation network
 size_t face_values(bool ion) { return ion ? NFACE + 1 : NFACE; }
 
-ZTile ztile_of(const Geo& g, int nt);
+ZTile ztile_of(const Geo& g, int nt, int txmax = 64);
 int ztile_blocks(const Geo& g, const ZTile& z);
 
 Layout layout_of(const int32_t n[3], int precision, bool grav, bool ion)
@@ -378,10 +378,10 @@ constexpr int ZMARCH_SEG = 32;
 
 // tiles of the z-marching update kernels: 64 x cells (a wave) by nt / 64
 // rows for blocks of nt threads, narrower for thin boxes
-ZTile ztile_of(const Geo& g, int nt)
+ZTile ztile_of(const Geo& g, int nt, int txmax)
 {
     ZTile z;
-    z.tx = g.nx < 64 ? g.nx : 64;
+    z.tx = g.nx < txmax ? g.nx : txmax;
     z.ty = nt / z.tx;
     z.ntx = (g.nx + z.tx - 1) / z.tx;
     z.nty = (g.ny + z.ty - 1) / z.ty;
@@ -491,7 +491,7 @@ void emit_nonadv_substage_t(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout
     ua.a = a;
     ua.rk = rk;
     ua.dbg = dbg;
-    ua.zt = ztile_of(g, UPD_NT);
+    ua.zt = ztile_of(g, UPD_NT, UPD_TX);
     ua.phi = phi;
     const int ublocks = ztile_blocks(g, ua.zt);
     if (rows)
@@ -568,7 +568,7 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
         xa.dbg = dbg;
         xz_tiling(b->g, xa.rpb, xa.nrg, xa.seg);
         const int blocks = xz_blocks(b->g);
-        auto shm = [](int nv, int nq) { return (size_t)2 * (nv + nq) * XZ_MAXT * sizeof(T); };
+        auto shm = [](int nv, int nq) { return (size_t)2 * (nv + 2 * nq) * XZ_MAXT * sizeof(T); };
         e.template launch<BAdvXZUpdate<T, 0, 4, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(4, 4), xa);   // rho, m
         if (ion) e.template launch<BAdvXZUpdate<T, 4, 4, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(6, 4), xa);
         else e.template launch<BAdvXZUpdate<T, 4, 3, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(5, 3), xa);

@@ -616,8 +616,10 @@ struct NonadvUpdateArgs {
     const T* phi;   // gravitational potential, or null without self-gravity
 };
 
-// threads per block of the NONADV update (its x-y tile is 64 x UPD_NT / 64)
+// threads per block of the NONADV update and the x width of its x-y tile
+// (UPD_TX x UPD_NT / UPD_TX cells)
 constexpr int UPD_NT = 256;
+constexpr int UPD_TX = 64;
 
 // FULL: all eight fields (the update of boxes whose x faces come from the
 // one-face-per-thread kernel); otherwise only the face fields b_x, b_y, b_z,
@@ -1507,10 +1509,13 @@ struct BAdvZUpdate {
 // as BAdvFaceXRow does (sqrt(rho)-weighted velocity, the upwind cell's
 // parabola from its 5-cell window at fixed row offsets, periodic inside the
 // row); the fluxes are exchanged through LDS for the x difference, so the x
-// fluxes never pass through memory.  Two block barriers per plane; the LDS is
-// double-buffered by plane parity, so a buffer is rewritten only after every
-// thread has passed the barriers that follow its last reads.  Dynamic LDS:
-// 2 x (NV + NQ) x NT values.  Threads beyond the block's rows (and the rows
+// fluxes never pass through memory.  Each cell's limited slope is formed once
+// by its own thread and shared through LDS (the per-face form computes the
+// three slopes of the upwind window from the same operands, so the results
+// are the same bits).  Three block barriers per plane (values, slopes,
+// fluxes); the LDS is double-buffered by plane parity, so a buffer is
+// rewritten only after every thread has passed the barriers that follow its
+// last reads.  Dynamic LDS: 2 x (NV + 2 NQ) x NT values.  Threads beyond the block's rows (and the rows
 // of a last, partial row group) reach every barrier: they read row 0 of the
 // block, which is always a real row, and write nothing, to LDS or memory.
 template <typename T>
@@ -1664,16 +1669,25 @@ struct BAdvXZUpdate {
                 dy[q] = A.Fy[o + cyp] - A.Fy[o + c];
                 sv[q] = A.S.f[fld[Q0 + q]][c];
             }
-            // x faces of plane x: publish the cell, form the flux of its
-            // lower x face, exchange the fluxes
-            T* vb = sm + (x & 1) * ((NV + NQ) * NT);
-            T* fb = vb + NV * NT;
+            // x faces of plane x: publish the cell, then its limited slope,
+            // form the flux of its lower x face, exchange the fluxes
+            T* vb = sm + (x & 1) * ((NV + 2 * NQ) * NT);
+            T* db = vb + NV * NT;
+            T* fb = db + NQ * NT;
             if (act) {
 #pragma unroll
                 for (int q = 0; q < NQ; q++) vb[q * NT + tme] = w[q][2];
                 if constexpr (!own_v) {
                     vb[RI * NT + tme] = vr[0];
                     vb[MXI * NT + tme] = vx[0];
+                }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < NQ; q++) {
+                    const T* u = vb + q * NT;
+                    db[q * NT + tme] = limited_slope(u[tx[2]], w[q][2], u[tx[4]]);
                 }
             }
             __syncthreads();
@@ -1685,14 +1699,19 @@ struct BAdvXZUpdate {
                 const T vf = (vb[MXI * NT + tx[2]] * rsl + vb[MXI * NT + tme] * rsr) * rcp_nr(rl * rsl + rr * rsr);
                 const bool upw = vf >= T(0);
                 const T y = upw ? ydx * vf : ydx * (-vf);
-                // the upwind cell's window: cells i-3 .. i+1 or i-2 .. i+2
+                // the upwind cell's window: cells i-3 .. i+1 or i-2 .. i+2;
+                // its slopes and those of its neighbours from LDS
                 int ix[5];
 #pragma unroll
                 for (int m = 0; m < 5; m++) ix[m] = upw ? tx[m] : tx[m + 1];
 #pragma unroll
                 for (int q = 0; q < NQ; q++) {
                     const T* u = vb + q * NT;
-                    Par<T> P = parabola(u[ix[0]], u[ix[1]], u[ix[2]], u[ix[3]], u[ix[4]]);
+                    const T* d = db + q * NT;
+                    const T u0 = u[ix[0]], u1 = u[ix[1]], u2 = u[ix[2]], u3 = u[ix[3]], u4 = u[ix[4]];
+                    const T dm_m = d[ix[1]], dm_0 = d[ix[2]], dm_p = d[ix[3]];
+                    Par<T> P = parabola_finish(u0, u1, u2, u3, u4, interface_value(u1, u2, dm_m, dm_0),
+                                               interface_value(u2, u3, dm_0, dm_p), dm_0);
                     T qup = upw ? avg_right(P, y) : avg_left(P, y);
                     fx[q] = vf * qup;
                     if (act) fb[q * NT + tme] = fx[q];
@@ -1794,6 +1813,8 @@ struct BReduceDt {
     {
         __shared__ double red[16];
         double m = 0.0;
+        // unrolled so that several independent loads are in flight
+#pragma unroll 8
         for (int t = tid; t < A.nparts; t += NT) m = A.part[t] > m ? A.part[t] : m;
         m = wave_max(m);
         if ((tid & 63) == 0) red[tid >> 6] = m;

@@ -142,8 +142,11 @@ __device__ __forceinline__ Par<T> parabola_finish(T qmm, T qm, T q0, T qp, T qpp
     T nL = flat ? q0 : (overL ? T(3) * q0 - T(2) * qR : qL);
     T nR = flat ? q0 : ((!overL && overR) ? T(3) * q0 - T(2) * qL : qR);
     // Step 4: discontinuity detector on second differences (h^2 cancels)
-    T qLp = q0 - T(0.25) * dm;
-    T qRp = q0 + T(0.25) * dm;
+    // q0 -/+ dm / 4 with one rounding each: dm / 2 is exact, and the fused
+    // product (dm / 2) / 2 is the exact dm / 4 (inline constants only)
+    const T hdm = T(0.5) * dm;
+    T qLp = fma(T(-0.5), hdm, q0);
+    T qRp = fma(T(0.5), hdm, q0);
     T Dm = q0 - T(2) * qm + qmm;
     T Dp = qpp - T(2) * qp + q0;
     T aqp = fabs(qp), aqm = fabs(qm);
