@@ -58,8 +58,18 @@ ALG_VALUES = {
 }
 
 
-def _config(name):
+def _config(name, n=None):
     from paper_1608_08748_amd import binding, inputs
+    if name == "c4r":
+        n = n or 256
+        return dict(desc="c4 recipe at %d^3: lognormal density sigma 1, rms Mach 10, beta 0.1, x_H2 1e-2, FP32 state/"
+                         "fluxes, FP64 chemistry/regularisation/CFL/totals, with its FP64 run" % n,
+                    n=n, gen=lambda: inputs.c4(n=n), precision=binding.FP32_MIXED, steps=50, dtype="f32+f64")
+    if n is not None and name in ("c2", "c3"):
+        base = _config(name)
+        gen = {"c2": inputs.c2, "c3": inputs.c3}[name]
+        base.update(n=n, gen=lambda: gen(n=n), desc=base["desc"].replace("%d^3" % base["n"], "%d^3" % n, 1))
+        return base
     if name == "c1":
         return dict(desc="c1: 32^3 periodic box, white-noise velocity sigma 0.1, B=(0.1,0,0), FP64",
                     n=32, gen=lambda: inputs.c1(), precision=binding.FP64, steps=10, dtype="f64")
@@ -177,6 +187,35 @@ def _step_roofline(cell_updates_per_s, esz):
     return {"alg_bytes_per_cell_update": per_cell, "achieved_gbs": round(gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
             "roofline_cell_updates_per_s": round(HBM_PEAK_GBS * 1e9 / per_cell, 1)}
+
+
+def _gate_stats(U, gamma=5.0 / 3.0):
+    """The two gates of the dual-energy sync (Sec. 2.8 with the pressure
+    gate): over the cells of a state after a step, the fractions where the
+    sync e := E - K - M ran (both gates open), where the pressure gate
+    (gamma - 1)(E - K - M) > B^2/2 kept e, and where the 1e-3 gate kept it;
+    and, over the cells the pressure gate kept, the internal energy that
+    total-energy conservation would have given minus the one the scheme
+    carries, relative to the total internal energy.  Host FP64 from the
+    stored values; constant gamma."""
+    import numpy as np
+    rho, E, e = U[0], U[4], U[5]
+    K = 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / rho
+    M = 0.0
+    for d in range(3):
+        bf = U[6 + d]
+        M = M + 0.125 * (bf + np.roll(bf, -1, axis=2 - d)) ** 2
+    ei = E - K - M
+    g1 = ei >= 1e-3 * E
+    g2 = (gamma - 1.0) * ei > M
+    kept_p = g1 & ~g2
+    n = float(rho.size)
+    return {"sync_fraction": float(np.count_nonzero(g1 & g2) / n),
+            "kept_by_pressure_gate_fraction": float(np.count_nonzero(kept_p) / n),
+            "kept_by_1e-3_gate_fraction": float(np.count_nonzero(~g1) / n),
+            "pressure_gate_energy_gap_rel": float((ei[kept_p] - e[kept_p]).sum() / e.sum()),
+            "pressure_gate_cells_mean_abs_gap_rel": float(np.mean(np.abs(ei[kept_p] - e[kept_p]) / e[kept_p]))
+            if kept_p.any() else 0.0}
 
 
 def _cpu_baseline(n=192, steps=3, cooling=False, grav_G=0.0, ionisation=False):
@@ -420,7 +459,7 @@ def _largest_box_bench(args):
 CONSERVED = ("rho", "mx", "my", "mz", "E", "bx", "by", "bz")
 
 
-def _precision_leg(W, shape, steps, warmup, dts, G64, t64, phys, workload):
+def _precision_leg(W, shape, steps, warmup, dts, G64, t64, phys, workload, gate=False):
     """FP32 state on the workload's state, replaying the FP64 run's dt
     sequence: throughput, per-kernel time, and the errors of every total and
     field against that FP64 run."""
@@ -446,6 +485,7 @@ def _precision_leg(W, shape, steps, warmup, dts, G64, t64, phys, workload):
     absq = np.abs(G64).reshape(binding.NFIELDS, -1).sum(axis=1)
     te = _total_errors(t32, t64, absq, nf)
     fe = _field_errors(G32, G64, nf)
+    gates = _gate_stats(G32) if gate else None
     del G32
     return {
         "value": round(ncell * steps / el, 1), "unit": "cell-updates/s", "ms_per_step": round(el / steps * 1e3, 3),
@@ -461,6 +501,7 @@ def _precision_leg(W, shape, steps, warmup, dts, G64, t64, phys, workload):
         "max_conserved_total_rel_err": max(te[f] for f in CONSERVED if f in te),
         "total_rel_err": te,
         "fp32_field_err": fe,
+        **({"regularisation_gates": gates} if gate else {}),
     }
 
 
@@ -469,11 +510,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c4r", "c5"])
+    ap.add_argument("--n", type=int, default=None, help="c2, c3, c4r: cells per axis (other than the configured)")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
                     help="c2: leave out the FP32 and serving legs of the line")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="time only the oracle on the c2 recipe (--cpu-n, --cpu-steps; threads from "
+                         "OMP_NUM_THREADS) and print its cpu_baseline object")
+    ap.add_argument("--cpu-n", type=int, default=192)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--gate-stats", action="store_true",
+                    help="c2, c3: add the regularisation gate statistics of the FP64 reference state")
     ap.add_argument("--cooling", action="store_true",
                     help="c1-c3: add the heating/cooling stage (Sec. 2 stage 5) after chemistry")
     ap.add_argument("--gravity", action="store_true",
@@ -486,6 +535,9 @@ def main():
         print("bench.py: this implementation runs one box on one GPU; --gpus %d is not supported "
               "(multi-GPU sharding is a design note only)" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
+    if args.cpu_only:
+        print(json.dumps({"cpu_baseline": _cpu_baseline(n=args.cpu_n, steps=args.cpu_steps)}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -501,9 +553,10 @@ def main():
         print(json.dumps(_largest_box_bench(args)), flush=True)
         return
 
-    cfg = _config(args.config)
+    cfg = _config(args.config, args.n)
     steps = args.steps if args.steps is not None else cfg["steps"]
     W = cfg["gen"]()
+    log("initial condition %s generated" % (W.shape[1:],))
     shape = W.shape[1:]
     ncell = int(np.prod(shape))
     torch.cuda.set_device(0)
@@ -519,7 +572,7 @@ def main():
     phys = dict(cooling=cool, grav_G=gG, ionisation=ion)
     workload = args.config + ("+gravity" if gG > 0 else "") + ("+ionisation" if ion else "")
     esz = 8 if cfg["precision"] == binding.FP64 else 4
-    legs = args.config == "c3" or (args.config == "c2" and not args.no_legs)
+    legs = args.config in ("c3", "c4r") or (args.config == "c2" and not args.no_legs)
 
     # the FP64 run with its dt sequence read back each step: the reference of
     # the FP32 errors (c3's FP64 figure is this run's rate)
@@ -534,16 +587,18 @@ def main():
         el64, ref_dts = _timed_run(ref, steps, record=True)
         t64 = ref.totals()
         G64 = ref.get_state()
+        if args.gate_stats:
+            extra["regularisation_gates"] = _gate_stats(G64)
         ref.close()
         del ref
         torch.cuda.empty_cache()
         log("FP64 reference run: %d steps, %.3f s" % (steps, el64))
-        if args.config == "c3":
+        if args.config in ("c3", "c4r"):
             extra["fp64_same_seed"] = {"value": round(ncell * steps / el64, 1),
                                        "ms_per_step": round(el64 / steps * 1e3, 3)}
 
-    if args.config == "c3":
-        leg = _precision_leg(W, shape, steps, args.warmup, ref_dts, G64, t64, phys, workload)
+    if args.config in ("c3", "c4r"):
+        leg = _precision_leg(W, shape, steps, args.warmup, ref_dts, G64, t64, phys, workload, gate=args.gate_stats)
         del G64
         out = {
             "metric": METRIC, "value": leg["value"], "unit": "cell-updates/s",
@@ -560,6 +615,8 @@ def main():
         out["fp32_total_rel_err"] = leg["total_rel_err"]
         out["fp32_field_err"] = leg["fp32_field_err"]
         out.update(extra)
+        if args.gate_stats:
+            out["regularisation_gates"] = {"fp64": extra["regularisation_gates"], "fp32": leg["regularisation_gates"]}
     else:
         box = binding.Box(shape, precision=cfg["precision"], **phys)
         box.init_state(W)
@@ -595,6 +652,7 @@ def main():
             # the timed run (device-resident dt) and the reference run (dt read
             # back) compute the same bits
             out["reference_run_bitwise"] = bool(np.array_equal(tot, t64))
+            out.update(extra)
             out["fp32_leg"] = _precision_leg(W, shape, steps, args.warmup, ref_dts, G64, t64, phys, workload)
             del G64
             log("FP32 leg done")

@@ -3,8 +3,8 @@
  * uniform periodic 3D grid, after Kulikov, Chernykh & Protasov (arXiv:1608.08748),
  * on one AMD MI355X (gfx950).
  *
- * The step (Sec. 2, stages 1-4 and 6 of the paper's list; no gravity, no
- * heating/cooling):
+ * The step (Sec. 2, the stages of the paper's list; heating/cooling, self-
+ * gravity and the ionisation network are options of mhd_params):
  *   NONADV  pressure, Lorentz force and p dV work by a linearised Riemann
  *           problem with local-parabola data at every face (Sec. 2.1, 2.4),
  *           with the face-centred magnetic field updated from edge electric
@@ -14,8 +14,13 @@
  *           each of the two stages is one three-stage SSP Runge-Kutta pass
  *           (Sec. 2.2);
  *   CHEM    semi-implicit H/H2 update per cell, reactions 1-4 (Sec. 2.7 and
- *           the rate appendix), always in FP64;
- *   REG     dual-energy regularisation (Sec. 2.8), always in FP64.
+ *           the rate appendix; with the ionisation network also H+ by
+ *           reactions 5-8, Sec. 4.3), always in FP64;
+ *   COOL    (option) explicit heating/cooling source (Sec. 2 stage 5,
+ *           Sec. 2.8), FP64;
+ *   REG     dual-energy regularisation (Sec. 2.8), always in FP64;
+ *   GRAV    (option) Poisson stage with the 27-point Green's function
+ *           (Sec. 2.9) and the gravity sources in NONADV.
  * The time step follows the CFL rule of Sec. 2.3.
  *
  * State (conserved, structure of arrays, x fastest, field order):

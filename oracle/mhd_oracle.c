@@ -59,7 +59,7 @@
  *            the Riemann velocity in NONADV but with the averaged velocity in
  *            ADV, and an unconditional sync feeds that mismatch into the
  *            pressure (it oscillates on the paper's shock tube of Sec. 3.1).
- *   R-chem   Sec. 2.7 + Appendix rates: H/H2 only (reactions 1-4); n_H =
+ *   R-chem   Sec. 2.7 + Appendix rates: H/H2 (reactions 1-4); n_H =
  *            n_u (rho - h2), n_H2 = n_u h2 / 2, C = k1 n_H^2 with k1 carrying its
  *            n/n_H factor (evaluated as k1' n n_H), D = k2 n_H + k3 n_H2 + k4,
  *            k4 optically thin; one semi-implicit update per step.
@@ -81,9 +81,8 @@
  *            exp(-a) with a = 1 + 1/(k_B T), k_B T in eV (the printed exp(+a)
  *            grows without bound as T -> 0, unlike an excitation rate, and
  *            gives cooling times of 1e7 s at 700 K).  Gamma4 = 6.4e-13 erg k4
- *            n_H2.  The
- *            terms of reactions 5-8 belong to the ionisation network, which
- *            is not built.
+ *            n_H2.  The terms of reactions 5-8 come with the ionisation
+ *            network (R-ion).
  *   R-grav   Sec. 2 equations, Sec. 2.4 and Sec. 2.9: Laplace(Phi) = 4 pi G
  *            rho; in harmonic space Phi_hat = -(2/3) pi G h^2 rho_hat /
  *            (1 - prod_d (3 - 2 sin^2(pi m_d / n_d)) / 3) (the printed form

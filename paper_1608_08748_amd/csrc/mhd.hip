@@ -394,23 +394,31 @@ int ztile_blocks(const Geo& g, const ZTile& z)
     return z.ntx * z.nty * ((g.nz + z.seg - 1) / z.seg);
 }
 
-// the ADV update forms the x faces itself when whole x rows fit its block
-constexpr int XZ_MAXT = 256;
+// The ADV update forms the x faces itself when whole x rows fit its block:
+// blocks of 256 threads, or 512 for longer rows, or 1024 for FP32 state (the
+// FP64 kernels need more than the 128 registers a 1024-thread block allows).
+int xz_block_threads(const Geo& g, size_t esz)
+{
+    if (g.nx <= 256) return 256;
+    if (g.nx <= 512) return 512;
+    if (g.nx <= 1024 && esz == 4) return 1024;
+    return 0;
+}
 
-bool adv_xz(const Geo& g) { return g.nx <= XZ_MAXT; }
+bool adv_xz(const Geo& g, size_t esz) { return xz_block_threads(g, esz) > 0; }
 
 // rows per block, row groups and z segment of the fused ADV update
-void xz_tiling(const Geo& g, int& rpb, int& nrg, int& seg)
+void xz_tiling(const Geo& g, size_t esz, int& rpb, int& nrg, int& seg)
 {
-    rpb = XZ_MAXT / g.nx;
+    rpb = xz_block_threads(g, esz) / g.nx;
     nrg = (g.ny + rpb - 1) / rpb;
     seg = g.nz < ZMARCH_SEG ? g.nz : ZMARCH_SEG;
 }
 
-int xz_blocks(const Geo& g)
+int xz_blocks(const Geo& g, size_t esz)
 {
     int rpb, nrg, seg;
-    xz_tiling(g, rpb, nrg, seg);
+    xz_tiling(g, esz, rpb, nrg, seg);
     return nrg * ((g.nz + seg - 1) / seg);
 }
 
@@ -543,6 +551,17 @@ void emit_adv_face(mhd_box* b, Emit& e, const Fields<T>& in, const StepArgs& a)
 }
 
 
+// the two field-group launches of the fused ADV update with blocks of NT
+// threads (dynamic LDS: 2 x (NV + 2 NQ) x NT values)
+template <typename T, int NT, class Emit>
+void emit_adv_xz(Emit& e, const AdvXZArgs<T>& xa, int blocks, bool ion)
+{
+    auto shm = [](int nv, int nq) { return (size_t)2 * (nv + 2 * nq) * NT * sizeof(T); };
+    e.template launch<BAdvXZUpdate<T, 0, 4, NT>>(MHD_K_ADV_UPDATE, blocks, shm(4, 4), xa);   // rho, m
+    if (ion) e.template launch<BAdvXZUpdate<T, 4, 4, NT>>(MHD_K_ADV_UPDATE, blocks, shm(6, 4), xa);
+    else e.template launch<BAdvXZUpdate<T, 4, 3, NT>>(MHD_K_ADV_UPDATE, blocks, shm(5, 3), xa);
+}
+
 // tail: the step's last substage, whose energy-group launch runs the tail of
 // the step and leaves the CFL speed maxima in b->part
 template <typename T, class Emit>
@@ -553,7 +572,7 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
     Fields<T> S = view<T>(b, sS.h, sS.m, sS.b);
     Fields<T> out = view<T>(b, sout.h, sout.m, sout.b);
     const bool ion = b->p.ionisation != 0;
-    if (adv_xz(b->g)) {
+    if (adv_xz(b->g, sizeof(T))) {
         // y faces marched along y; the x faces inside the z-marching update
         if (ion) emit_adv_face<T, 1, 8>(b, e, in, a);
         else emit_adv_face<T, 1, 7>(b, e, in, a);
@@ -566,12 +585,11 @@ void emit_adv_substage(mhd_box* b, Emit& e, Slots sin, Slots sS, Slots sout, con
         xa.a = a;
         xa.rk = rk;
         xa.dbg = dbg;
-        xz_tiling(b->g, xa.rpb, xa.nrg, xa.seg);
-        const int blocks = xz_blocks(b->g);
-        auto shm = [](int nv, int nq) { return (size_t)2 * (nv + 2 * nq) * XZ_MAXT * sizeof(T); };
-        e.template launch<BAdvXZUpdate<T, 0, 4, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(4, 4), xa);   // rho, m
-        if (ion) e.template launch<BAdvXZUpdate<T, 4, 4, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(6, 4), xa);
-        else e.template launch<BAdvXZUpdate<T, 4, 3, XZ_MAXT>>(MHD_K_ADV_UPDATE, blocks, shm(5, 3), xa);
+        xz_tiling(b->g, sizeof(T), xa.rpb, xa.nrg, xa.seg);
+        const int nt = xz_block_threads(b->g, sizeof(T));
+        if (nt == 256) emit_adv_xz<T, 256>(e, xa, xz_blocks(b->g, sizeof(T)), ion);
+        else if (nt == 512) emit_adv_xz<T, 512>(e, xa, xz_blocks(b->g, sizeof(T)), ion);
+        else if constexpr (sizeof(T) == 4) emit_adv_xz<T, 1024>(e, xa, xz_blocks(b->g, sizeof(T)), ion);
         return;
     }
     // x faces from staged row segments, one face per thread; y faces marched
@@ -759,7 +777,7 @@ void emit_step(mhd_box* b, Emit& e, const StepArgs& a)
 {
     if (b->grav) emit_poisson<T>(b, e);
     emit_nonadv_stage<T>(b, e, a, true);
-    if (adv_xz(b->g)) {
+    if (adv_xz(b->g, sizeof(T))) {
         // the fused ADV update forms x faces at every plane; with the tail's
         // FP64 chemistry on top it would spill, so the tail is a pass of its
         // own (the same arithmetic)
