@@ -263,21 +263,27 @@ template <typename T> struct FluxDiff { static constexpr bool v = sizeof(T) == 4
 // Runge-Kutta combination of m, E, e (Sec. 2.2).  Only the edge-field
 // components of the x faces are stored, for the face-field update.  Dynamic
 // LDS: XROW_SLOTS x NT values, value k of thread t at k * NT + t: primitives
-// in slots 0-7 with sqrt(rho) in 14, slopes 8-13, interface values 0-5,
-// parabola sides 6-23 and x-face fluxes 0-4, so each exchange needs one
-// barrier.
-constexpr int XROW_SLOTS = 24;
+// in slots 0-7 with sqrt(rho) in 14, slopes 8-13, the two edge values of each
+// parabola in 0-7 and 14-17 (the right neighbour forms the left cell's jump
+// and curvature from them and the mean it holds, with the expressions of
+// parabola_finish, so the same bits) and x-face fluxes 8-12, so each exchange
+// needs one barrier.
+constexpr int XROW_SLOTS = 18;
 
 template <typename T, int MAXT, bool ION>
 struct BFaceXRows {
     static constexpr int NT = MAXT;
     static constexpr bool XCD = false;
+    // FP64 rows of 512 cells: two blocks per CU (72 KB of LDS each) need four
+    // waves per SIMD, i.e. at most 128 registers; the few values that spill
+    // cost less than the waiting of a single block at its barriers
+    static constexpr int MINW = (MAXT == 512 && sizeof(T) == 8) ? 4 : 1;
     using Args = FaceArgs<T>;
-    // LDS slot of component k (qR, dq, q6) of variable v's published right
-    // side: slots 0-7 and 14-23, around the slopes in 8-13
+    // LDS slot of edge value k (qL, qR) of variable v's published parabola:
+    // slots 0-7 and 14-17, around the slopes in 8-13
     static __device__ __forceinline__ constexpr int sslot(int v, int k)
     {
-        return 3 * v + k < 8 ? 3 * v + k : 3 * v + k + 6;
+        return 2 * v + k < 8 ? 2 * v + k : 2 * v + k + 6;
     }
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -343,8 +349,8 @@ struct BFaceXRows {
         __syncthreads();
         // interface values at both faces from the neighbours' slopes (the
         // upper one is the right cell's lower one, formed from the same
-        // operands), then the own cell's parabolas; the right side is
-        // published in the slots sslot(v, 0..2) (0-7 and 14-23: the
+        // operands), then the own cell's parabolas; their edge values are
+        // published in the slots sslot(v, 0..1) (0-7 and 14-17: the
         // primitives, densities and gamma there are no longer read; the
         // slopes in 8-13 are read until the barrier below)
         Side<T> R;
@@ -355,9 +361,8 @@ struct BFaceXRows {
                 T fr = interface_value(q2[v], q3[v], dm[v], sm[(8 + v) * NT + tr]);
                 Par<T> P = parabola_finish(q0[v], q1[v], q2[v], q3[v], q4[v], fl[v], fr, dm[v]);
                 side_right(P, R, v);
-                sm[sslot(v, 0) * NT + tid] = P.qR;
-                sm[sslot(v, 1) * NT + tid] = P.dq;
-                sm[sslot(v, 2) * NT + tid] = P.q6;
+                sm[sslot(v, 0) * NT + tid] = P.qL;
+                sm[sslot(v, 1) * NT + tid] = P.qR;
             }
         }
         __syncthreads();
@@ -365,12 +370,15 @@ struct BFaceXRows {
         // read before the barrier)
         T out[7];
         if (act) {
+            // the left cell's right side (Step 5 of parabola_finish on its
+            // edge values and its mean q1)
             Side<T> L;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
-                L.e[v] = sm[sslot(v, 0) * NT + tl];
-                L.dq[v] = sm[sslot(v, 1) * NT + tl];
-                L.q6[v] = sm[sslot(v, 2) * NT + tl];
+                const T fL = sm[sslot(v, 0) * NT + tl], fR = sm[sslot(v, 1) * NT + tl];
+                L.e[v] = fR;
+                L.dq[v] = fR - fL;
+                L.q6[v] = T(6) * (q1[v] - T(0.5) * (fL + fR));
             }
             // parabola variables 3, 4, 5 are Bt1, Bt2, p
             face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
