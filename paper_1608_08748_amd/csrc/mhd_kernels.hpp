@@ -310,11 +310,28 @@ struct BFaceXRows {
         const int dzp = ((k + 1 == g.nz ? 0 : k + 1) - k) * g.nxy;
 
         // own cell: conserved values, primitives
-        T q2[6], rho = T(0), gam = gm, bn = T(0), srho = T(0);
+        // uc, sc: the cell's m, E, e at the substage input and at the stage
+        // start, for the update at the end.  With EARLY they are taken here
+        // (FP64 rows of 256 cells: the registers still fit three waves per
+        // SIMD, and the stores of the face outputs in between would make the
+        // compiler load them again); otherwise loaded at the update (FP32
+        // would drop from six to five waves, the 512-cell rows would spill)
+        constexpr bool EARLY = sizeof(T) == 8 && MAXT == 256;
+        T q2[6], rho = T(0), gam = gm, bn = T(0), srho = T(0), uc[5], sc[5];
+        const int upd[5] = { MX, MY, MZ, EN, EI };
         if (act) {
             Raw<T> rw;
             raw_load<T, 0, ION>(A.U, c, c + dyp, c + dzp, rw);
             bn = A.U.f[BX][c];
+            if constexpr (EARLY) {
+                uc[0] = rw.mn;
+                uc[1] = rw.m1;
+                uc[2] = rw.m2;
+                uc[3] = A.U.f[EN][c];
+                uc[4] = rw.e;
+#pragma unroll
+                for (int q = 0; q < 5; q++) sc[q] = A.S.f[upd[q]][c];
+            }
             raw_prim<T, ION>(rw, A.a.gamma, q2, gam);
             rho = rw.rho;
 #pragma unroll
@@ -391,6 +408,15 @@ struct BFaceXRows {
         __syncthreads();
         if (!act) return;
 
+        if constexpr (!EARLY) {
+            // all loads before the first store (outputs may alias inputs as
+            // far as the compiler knows)
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                uc[q] = A.U.f[upd[q]][c];
+                sc[q] = A.S.f[upd[q]][c];
+            }
+        }
         // update of m, E, e: flux differences of the x faces (the right
         // cell's lower face from LDS), y and z faces (memory)
         const T dtdx = T(step_dt(A.a) / A.a.h);
@@ -417,7 +443,7 @@ struct BFaceXRows {
         T divv = (dF[0][4] + dF[1][4]) + dF[2][4];
         // (gamma - 1) e, with the cell's gamma_eff under the network
         const T gm1 = ION ? gam - T(1) : T(A.a.gamma - 1.0);
-        inc[4] = -gm1 * A.U.f[EI][c] * dtdx * divv;
+        inc[4] = -gm1 * uc[4] * dtdx * divv;
         if (A.phi) {
             // self-gravity (Sec. 2 equations, Sec. 2.4): -rho grad(Phi) on
             // m and -m . grad(Phi) on E, central differences
@@ -433,11 +459,10 @@ struct BFaceXRows {
 #pragma unroll
             for (int a = 0; a < 3; a++) {
                 inc[a] -= dt * rho * gv[a];
-                work += A.U.f[MX + a][c] * gv[a];
+                work += uc[a] * gv[a];
             }
             inc[3] -= dt * work;
         }
-        const int upd[5] = { MX, MY, MZ, EN, EI };
         if (A.dbg) {
 #pragma unroll
             for (int q = 0; q < 5; q++) A.O.f[upd[q]][c] = inc[q];
@@ -446,16 +471,8 @@ struct BFaceXRows {
             if (ION) A.O.f[HP][c] = T(0);   // H+ is a field of its own only with the network
         } else {
             const T ra = T(A.rk.a), rb = T(A.rk.b);
-            // all loads before the first store (outputs may alias inputs as
-            // far as the compiler knows)
-            T uv[5], sv[5];
 #pragma unroll
-            for (int q = 0; q < 5; q++) {
-                uv[q] = A.U.f[upd[q]][c];
-                sv[q] = A.S.f[upd[q]][c];
-            }
-#pragma unroll
-            for (int q = 0; q < 5; q++) A.O.f[upd[q]][c] = (uv[q] + ra * (sv[q] - uv[q])) + rb * inc[q];
+            for (int q = 0; q < 5; q++) A.O.f[upd[q]][c] = (uc[q] + ra * (sc[q] - uc[q])) + rb * inc[q];
         }
     }
 };
