@@ -142,7 +142,7 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 TRAFFIC = {
     # average of the x-row (with the m, E, e update), y-march and z-march
     # face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("5e7e9e1e700bc3cb", 3307752370),
+    ("c2", 8, "nonadv_face"): ("726d52ceefb3442e", 3128607211),
 }
 
 

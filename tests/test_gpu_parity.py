@@ -310,3 +310,25 @@ def test_c2_full_size_first_steps():
     tg, to = box.totals(), oracle.totals(P, U)
     absq = np.abs(U).reshape(binding.NFIELDS, -1).sum(axis=1)
     assert np.all(np.abs(tg - to) <= TOL64 * absq), (tg - to) / np.maximum(absq, 1e-300)
+
+
+@pytest.mark.parametrize("shape", [(3, 2, 40), (2, 3, 300), (2, 2, 520)])
+def test_adv_rhs_at_each_row_dispatch(shape):
+    # the ADV right-hand side where the update forms the x faces itself with
+    # 256-thread blocks holding several rows (nx = 40) or 512-thread blocks
+    # (nx = 300), and where rows exceed a block (nx = 520, FP64: the x faces
+    # as a kernel of their own); and the NONADV right-hand side beside it
+    W = inputs.white_noise(shape, seed=41, sigma=0.4, B=(0.2, -0.1, 0.3))
+    W[0] *= 1.0 + 0.3 * np.random.default_rng(42).random(shape)
+    P = oracle.make_params(shape)
+    U = oracle.prim_to_cons(P, W)
+    dt = oracle.cfl_dt(P, U)
+    box = binding.Box(shape)
+    for stage, ref in ((binding.STAGE_ADV_RHS, oracle.adv_rhs(P, U, dt)),
+                       (binding.STAGE_NONADV_RHS, oracle.nonadv_rhs(P, U, dt))):
+        box.set_state(U)
+        box.debug_stage(stage, dt)
+        G = box.get_state()
+        for f in range(binding.NFIELDS):
+            scale = max(np.abs(ref[f]).sum(), 1e-300)
+            assert np.abs(G[f] - ref[f]).sum() <= TOL64 * scale + 1e-300, (stage, binding.FIELDS[f])
