@@ -258,16 +258,18 @@ def _total_errors(ta, tb, absq, nf):
     return {binding.FIELDS[f]: float(abs(ta[f] - tb[f]) / absq[f]) for f in range(nf) if absq[f] > 0}
 
 
-def _serving(requests, steps, budget_run=False, sample=4):
+def _serving(requests, steps, budget_run=False, sample=4, persistent=True):
     """c5: requests with sizes {32,48,64,96,128}^3, rms Mach U[1,10], beta
     U[0.1,10], x_H2 log-uniform [1e-4,1e-1], `steps` steps each, FP32 state
     with FP64 chemistry; saturated run (all at t = 0) for the capacity, then
     Poisson arrivals at 0.8 of it for the latencies (and, with budget_run, a
     2 GB HBM budget).  Request states sit in pinned host memory and are lent
-    to the server (no copy at submission; one DMA each at admission).  For
-    `sample` requests of distinct sizes the served FP32 result is compared
-    with the plain FP64 step of the same request on the same GPU (each at its
-    own CFL steps)."""
+    to the server (no copy at submission; one DMA each at admission).  The
+    merged launches are persistent (a resident grid claims the union of the
+    boxes' tiles) unless persistent=False; the saturated run is repeated with
+    the other launch form for comparison.  For `sample` requests of distinct
+    sizes the served FP32 result is compared with the plain FP64 step of the
+    same request on the same GPU (each at its own CFL steps)."""
     import numpy as np
     import torch
     from paper_1608_08748_amd import binding, inputs, serving
@@ -291,8 +293,8 @@ def _serving(requests, steps, budget_run=False, sample=4):
         first.setdefault(r["n"], i)
     keep = [first[n] for n in sorted(first)][:sample]
 
-    def one(budget, slots, arrivals, keep_idx=()):
-        sv = binding.Server(budget, max_slots=slots, precision=binding.FP32_MIXED)
+    def one(budget, slots, arrivals, keep_idx=(), pers=persistent):
+        sv = binding.Server(budget, max_slots=slots, precision=binding.FP32_MIXED, persistent=pers)
         out = serving.run(sv, states, steps, arrivals=arrivals, borrow=True, keep_state=set(keep_idx))
         kept = {i: sv.result(out["records"][i]["id"]) for i in keep_idx}
         _, peak, cap = sv.memory()
@@ -303,12 +305,14 @@ def _serving(requests, steps, budget_run=False, sample=4):
         out["pool_bytes"] = cap
         return out
 
-    # warm-up: a few requests through the merged kernels
-    sv = binding.Server(4 << 30, max_slots=8, precision=binding.FP32_MIXED)
-    serving.run(sv, states[:4], 2, borrow=True)
-    sv.close()
+    # warm-up: a few requests through the merged kernels of both forms
+    for pers in (False, True):
+        sv = binding.Server(4 << 30, max_slots=8, precision=binding.FP32_MIXED, persistent=pers)
+        serving.run(sv, states[:4], 2, borrow=True)
+        sv.close()
     budget, slots = 64 << 30, 128
     sat = one(budget, slots, None)
+    sat_other = one(budget, slots, None, pers=not persistent)
     req_rate = 0.8 * sat["throughput"] / (mean_cells * steps)
     arr = serving.poisson_arrivals(len(states), req_rate, seed=5)
     poi = one(budget, slots, arr, keep)
@@ -352,8 +356,11 @@ def _serving(requests, steps, budget_run=False, sample=4):
         "value": round(poi["throughput"], 1), "unit": "cell-updates/s", "requests": len(states), "steps": steps,
         "latency_p50_s": round(poi["latency_p50"], 4), "latency_p99_s": round(poi["latency_p99"], 4),
         "arrival_rate_per_s": round(req_rate, 3), "hbm_budget_bytes": budget, "max_slots": slots,
+        "launches": "persistent" if persistent else "one workgroup per tile",
         "poisson": {k: poi[k] for k in keys},
         "saturated": {k: sat[k] for k in keys},
+        ("saturated_one_workgroup_per_tile" if persistent else "saturated_persistent"):
+            {k: sat_other[k] for k in keys},
         "fp32_vs_fp64": {"what": "served FP32 result after %d steps against the plain FP64 step of the same "
                                  "request (single box, FP64 state), each at the CFL steps of its own state; an "
                                  "FP32 single box reproduces the served bits (served_equals_single_box); totals "
@@ -374,7 +381,7 @@ def _serving(requests, steps, budget_run=False, sample=4):
 def _serving_bench(args):
     """The serving workload as the line's headline."""
     steps = args.steps if args.steps is not None else 50
-    sv = _serving(args.requests, steps, budget_run=True)
+    sv = _serving(args.requests, steps, budget_run=True, persistent=args.launch == "persistent")
     return {
         "metric": METRIC, "value": sv["value"], "unit": "cell-updates/s",
         "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
@@ -384,7 +391,7 @@ def _serving_bench(args):
                                "Poisson arrivals at 0.8 x saturated capacity" % (sv["requests"], steps),
                    "hbm_budget_bytes": sv["hbm_budget_bytes"], "max_slots": sv["max_slots"],
                    "request_states": "pinned host memory, lent",
-                   "parallelism": "single GPU, merged multi-box launches"},
+                   "parallelism": "single GPU, %s multi-box launches" % sv["launches"]},
         "serving": sv,
     }
 
@@ -516,6 +523,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c4r", "c5"])
     ap.add_argument("--n", type=int, default=None, help="c2, c3, c4r: cells per axis (other than the configured)")
     ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--launch", default="persistent", choices=["persistent", "tile"],
+                    help="serving: persistent multi-box launches, or one workgroup per tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
                     help="c2: leave out the FP32 and serving legs of the line")
@@ -659,7 +668,7 @@ def main():
             out["fp32_leg"] = _precision_leg(W, shape, steps, args.warmup, ref_dts, G64, t64, phys, workload)
             del G64
             log("FP32 leg done")
-            out["serving_leg"] = _serving(args.requests, 50)
+            out["serving_leg"] = _serving(args.requests, 50, persistent=args.launch == "persistent")
             log("serving leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(cooling=cool, grav_G=gG, ionisation=ion)

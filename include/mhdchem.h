@@ -247,7 +247,8 @@ const char *mhd_strerror(int status);
  * up (the caller's workspace is the HBM budget; every box lives inside it),
  * their state stays resident in HBM, and each call of mhd_server_progress
  * advances every box in flight by one step of its own CFL dt with one merged
- * launch per kernel of the step program for all boxes.  A box computes
+ * launch per kernel of the step program for all boxes (persistent: a resident
+ * grid walks the union of the boxes' tiles).  A box computes
  * exactly the same bits alone or in any mix (same kernels, same per-box block
  * decomposition and reductions).  Boxes use the server's physics parameters;
  * n[0] <= 256.  Latencies are host wall-clock seconds since
@@ -264,6 +265,15 @@ typedef struct {
     void *workspace;         /* device memory, 256-byte aligned: the HBM budget */
     size_t workspace_bytes;  /* (mhd_server_reserved_bytes of it hold the launch */
                              /* tables, the rest is the box pool)                */
+    int32_t persistent;      /* 0: each merged launch takes one workgroup per    */
+                             /*    tile of the union of the boxes' tiles;        */
+                             /* 1: persistent launches: the grid is what the    */
+                             /*    chip holds at once and each workgroup walks   */
+                             /*    the tile list (same tiles, same bits)         */
+    int32_t max_workgroups;  /* persistent launches: at most this many          */
+                             /*    workgroups per launch (0: no cap beyond what  */
+                             /*    the chip holds), e.g. to leave compute units  */
+                             /*    to other work on the device                   */
 } mhd_server_params;
 
 typedef struct {

@@ -65,6 +65,8 @@ class ServerParams(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+        ("persistent", ctypes.c_int32),
+        ("max_workgroups", ctypes.c_int32),
     ]
 
 
@@ -301,13 +303,15 @@ def conserved_totals_noalloc(state, precision, out, stream=None):
 
 
 def server_params(precision=FP32_MIXED, gamma=5.0 / 3.0, cfl=0.3, theta=1.0, chemistry=True, units=None,
-                  max_slots=64, cooling=False):
+                  max_slots=64, cooling=False, persistent=True, max_workgroups=0):
     p = ServerParams()
     p.precision, p.gamma, p.cfl, p.theta = precision, gamma, cfl, theta
     p.chemistry = 1 if chemistry else 0
     p.cooling = 1 if cooling else 0
     p.n_unit_cm3, p.T_unit_K, p.t_unit_s = units if units is not None else DEFAULT_UNITS
     p.max_slots = max_slots
+    p.persistent = 1 if persistent else 0
+    p.max_workgroups = max_workgroups
     return p
 
 

@@ -20,6 +20,7 @@
 // all boxes), so a box gets the same bits alone or in a batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
@@ -326,11 +327,14 @@ struct OneEmit {
 // one program position merged over many boxes
 struct MultiRec {
     void (*go)(const void* tab, const int* bstart, int nbox, int blocks, size_t shm, hipStream_t s);
+    int (*go_persist)(const void* tab, const int* bstart, int nbox, int blocks, size_t shm, hipStream_t s, int ncu,
+                      int cap, int* next);
     std::vector<char> args;
     std::vector<int> bstart;
     int total;
     size_t shm;
     size_t off_args, off_bstart;   // offsets in the uploaded table
+    size_t off_next;               // the launch's tile counter (uploaded as 0; persistent launches)
 };
 
 template <class Body>
@@ -340,6 +344,49 @@ void go_many(const void* tab, const int* bstart, int nbox, int blocks, size_t sh
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_many<Body>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     k_many<Body><<<blocks, Body::NT, shm, s>>>(reinterpret_cast<const typename Body::Args*>(tab), bstart, nbox);
+}
+
+// resident workgroups per CU of k_persist<Body> with shm bytes of dynamic
+// LDS (the occupancy query runs once per body and LDS size)
+template <class Body>
+int persist_per_cu(size_t shm)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<size_t, int>> known;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto& kv : known)
+        if (kv.first == shm) return kv.second;
+    const void* f = reinterpret_cast<const void*>(&k_persist<Body>);
+    if (shm > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, Body::NT, shm) != hipSuccess || nb < 1) return 0;
+    known.push_back(std::make_pair(shm, nb));
+    return nb;
+}
+
+// claims of tiles per workgroup of a persistent launch: the last claims
+// balance the workgroups to within 1 / PERSIST_CLAIMS of their share
+constexpr int PERSIST_CLAIMS = 8;
+
+template <class Body>
+int go_persist(const void* tab, const int* bstart, int nbox, int blocks, size_t shm, hipStream_t s, int ncu,
+               int max_wg, int* next)
+{
+    if constexpr (!Persists<Body>::v) {
+        go_many<Body>(tab, bstart, nbox, blocks, shm, s);
+        return MHD_OK;
+    } else {
+        const int per_cu = persist_per_cu<Body>(shm);
+        if (per_cu < 1) return MHD_EDEVICE;
+        long cap = (long)per_cu * ncu;
+        if (max_wg > 0 && max_wg < cap) cap = max_wg;
+        const int grid = blocks < cap ? blocks : (int)cap;
+        // about PERSIST_CLAIMS claims per workgroup
+        const int chunk = std::max(1, blocks / (grid * PERSIST_CLAIMS));
+        k_persist<Body><<<grid, Body::NT, shm, s>>>(reinterpret_cast<const typename Body::Args*>(tab), bstart, nbox,
+                                                   blocks, chunk, next);
+        return MHD_OK;
+    }
 }
 
 struct MultiEmit {
@@ -353,9 +400,10 @@ struct MultiEmit {
         if (first) {
             MultiRec r;
             r.go = &go_many<Body>;
+            r.go_persist = &go_persist<Body>;
             r.total = 0;
             r.shm = 0;
-            r.off_args = r.off_bstart = 0;
+            r.off_args = r.off_bstart = r.off_next = 0;
             recs->push_back(r);
         }
         if (k >= recs->size() || (*recs)[k].go != &go_many<Body>) {
@@ -980,6 +1028,7 @@ struct mhd_server {
     hipEvent_t ev[2];
     int ev_ready;
     int64_t rounds;        // rounds launched
+    int ncu;               // compute units of the server's device (persistent launches)
     bool prev_launched;    // the previous call launched a round (event ev[(rounds - 1) & 1])
 };
 
@@ -1115,6 +1164,9 @@ int server_step(mhd_server* sv, int half)
         off = align256(off);
         r.off_bstart = off;
         off += r.bstart.size() * sizeof(int);
+        off = align256(off);
+        r.off_next = off;
+        off += sizeof(int);
     }
     if (off > SERVER_TAB_BYTES) return MHD_ENOMEM;
     char* h = sv->htab + (size_t)half * SERVER_TAB_BYTES;
@@ -1122,12 +1174,20 @@ int server_step(mhd_server* sv, int half)
     for (MultiRec& r : sv->recs) {
         memcpy(h + r.off_args, r.args.data(), r.args.size());
         memcpy(h + r.off_bstart, r.bstart.data(), r.bstart.size() * sizeof(int));
+        memset(h + r.off_next, 0, sizeof(int));
     }
     if (hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, sv->s) != hipSuccess) return MHD_EDEVICE;
     int nbox = (int)sv->active.size();
     for (MultiRec& r : sv->recs) {
         if (r.total == 0) continue;
-        r.go(d + r.off_args, reinterpret_cast<const int*>(d + r.off_bstart), nbox, r.total, r.shm, sv->s);
+        const int* bs = reinterpret_cast<const int*>(d + r.off_bstart);
+        if (sv->p.persistent) {
+            int st = r.go_persist(d + r.off_args, bs, nbox, r.total, r.shm, sv->s, sv->ncu, sv->p.max_workgroups,
+                                  reinterpret_cast<int*>(d + r.off_next));
+            if (st) return st;
+        } else {
+            r.go(d + r.off_args, bs, nbox, r.total, r.shm, sv->s);
+        }
     }
     return launch_status();
 }
@@ -1467,6 +1527,12 @@ int mhd_server_create(const mhd_server_params* p, mhd_server** out)
                        p->T_unit_K, p->t_unit_s))
         return MHD_EINVAL;
     if (p->max_slots < 1 || p->max_slots > SERVER_MAX_SLOTS) return MHD_EINVAL;
+    if (p->persistent != 0 && p->persistent != 1) return MHD_EINVAL;
+    if (p->max_workgroups < 0) return MHD_EINVAL;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        return MHD_EDEVICE;
     if (!p->workspace || p->workspace_bytes < 2 * SERVER_TAB_BYTES + 4096) return MHD_ENOMEM;
     if (((uintptr_t)p->workspace) & 255) return MHD_EINVAL;
     mhd_server* sv = new (std::nothrow) mhd_server;
@@ -1482,6 +1548,7 @@ int mhd_server_create(const mhd_server_params* p, mhd_server** out)
     sv->t0 = now_s();
     sv->htab = nullptr;
     sv->rounds = 0;
+    sv->ncu = ncu;
     sv->prev_launched = false;
     sv->ev_ready = 0;
     if (hipHostMalloc(reinterpret_cast<void**>(&sv->htab), SERVER_HOST_BYTES, hipHostMallocDefault) != hipSuccess) {

@@ -1,5 +1,7 @@
-"""Serving on the GPU: merged multi-box launches give every box exactly the
-bits it gets alone (and the same bits as the single-box API), served FP64
+"""Serving on the GPU: merged multi-box launches (persistent: a resident grid
+claims the union of the boxes' tiles; the binding's default) give every box
+exactly the bits it gets alone (and the same bits as the single-box API),
+launches of one workgroup per tile the same bits again, served FP64
 boxes of several sizes in one mix match the oracle, admission keeps the pool
 within the HBM budget, and a faulty request does not disturb the others."""
 import numpy as np
@@ -24,8 +26,8 @@ def _states():
             inputs.turbulence(24, seed=33, mach=6.0, beta=0.3, x_h2=1e-2)]
 
 
-def _serve(states, precision, steps=3, budget=1 << 30, max_slots=8):
-    sv = binding.Server(budget, max_slots=max_slots, precision=precision)
+def _serve(states, precision, steps=3, budget=1 << 30, max_slots=8, **launch):
+    sv = binding.Server(budget, max_slots=max_slots, precision=precision, **launch)
     out = serving.run(sv, states, steps, keep_state=True)
     res = [sv.result(sv_id) for sv_id in [r["id"] for r in out["records"]]]
     sv.close()
@@ -182,3 +184,41 @@ def test_served_fp64_boxes_match_oracle():
         absq = np.abs(U).reshape(binding.NFIELDS, -1).sum(axis=1)
         assert np.all(np.abs(np.asarray(rec["totals"]) - to) <= 1e-12 * absq)
         print("served box %s vs oracle: worst field L1 rel %.1e" % (W.shape[1:], worst), flush=True)
+
+
+@pytest.mark.parametrize("precision", [binding.FP64, binding.FP32_MIXED])
+@pytest.mark.parametrize("max_workgroups", [0, 1, 3, 7])
+def test_persistent_launches_equal_merged(precision, max_workgroups):
+    # a resident grid of at most max_workgroups workgroups (0: what the chip
+    # holds) walks the union of the boxes' tiles: a few workgroups take many
+    # tiles each, across box boundaries, with the LDS reused tile after tile
+    states = _states()
+    merged, merged_res = _serve(states, precision, persistent=False)
+    pers, pers_res = _serve(states, precision, persistent=True, max_workgroups=max_workgroups)
+    assert pers["max_active"] == 3
+    for i in range(len(states)):
+        np.testing.assert_array_equal(pers_res[i], merged_res[i])
+        np.testing.assert_array_equal(pers["records"][i]["totals"], merged["records"][i]["totals"])
+        assert pers["records"][i]["status"] == 0
+
+
+def test_persistent_launches_with_uneven_boxes_and_arrivals():
+    # boxes of five sizes arriving over time, so the mix (and the tile list)
+    # changes from round to round; each result equals its single-box run
+    states = [inputs.turbulence(n, seed=70 + n, mach=4.0, beta=0.5, x_h2=1e-3) for n in (8, 12, 16, 20, 24)]
+    sv = binding.Server(1 << 30, max_slots=3, precision=binding.FP32_MIXED, persistent=True, max_workgroups=5)
+    out = serving.run(sv, states, 4, arrivals=[0.0, 0.0, 0.01, 0.02, 0.02], keep_state=True)
+    res = [sv.result(r["id"]) for r in out["records"]]
+    sv.close()
+    for W, G in zip(states, res):
+        box = binding.Box(W.shape[1:], precision=binding.FP32_MIXED)
+        box.init_state(W)
+        for _ in range(4):
+            box.step_cfl()
+        np.testing.assert_array_equal(box.get_state(), G)
+
+
+def test_persistent_flags_rejected():
+    for kw in ({"persistent": True, "max_workgroups": -1},):
+        with pytest.raises(binding.MhdError):
+            binding.Server(1 << 28, max_slots=2, precision=binding.FP32_MIXED, **kw)
