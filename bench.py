@@ -142,7 +142,7 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 TRAFFIC = {
     # average of the x-row (with the m, E, e update), y-march and z-march
     # face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("726d52ceefb3442e", 3128607211),
+    ("c2", 8, "nonadv_face"): ("f8aee1e921d2f6bf", 3128630126),
 }
 
 

@@ -1210,16 +1210,24 @@ struct BAdvFaceXRow {
 };
 
 // ADV faces along y, marched: each thread walks one y line over a segment of
-// `seg` faces with a sliding 5-cell window of the NQ fields, so each cell's
+// `seg` cells with a sliding 5-cell window of the NQ fields, so each cell's
 // limited slope, lower interface value and parabola are formed once (the
 // per-face kernel forms three slopes, two interface values and a parabola per
 // face); the previous cell's right side and sqrt(rho) are carried.  The face
 // takes the upwind average: the left cell's right part for vf >= 0, the right
-// cell's left part otherwise (the same arithmetic as the x faces).
+// cell's left part otherwise (the same arithmetic as the x faces).  What is
+// stored is each cell's flux difference F(upper face) - F(lower face), the
+// value the update takes, so the segment forms one face more than it has
+// cells (the upper face of its last cell, also formed by the next segment
+// from the same window) and the update reads one value per field instead of
+// two.
 template <typename T, int NQ>
 struct BAdvFaceMarchY {
     static constexpr int NT = NTH;
     static constexpr bool XCD = false;
+    // two waves per SIMD (FP64 needs 220-230 registers; unbounded, the
+    // scheduler may take a few more and halve that)
+    static constexpr int MINW = sizeof(T) == 8 ? 2 : 1;
     struct Args {
         Geo g;
         CFields<T> U;
@@ -1283,21 +1291,27 @@ struct BAdvFaceMarchY {
             for (int q = 0; q < NQ; q++) nw[q] = A.U.f[fld[q]][cn];
         };
         fetch(x0);
-        for (int x = x0; x < x1; x++) {
+        // the flux of the lower face of the cell before x: in registers, or
+        // in the thread's own LDS slots where registers would not leave two
+        // waves per SIMD (FP64 with the H+ field)
+        constexpr bool PREV_LDS = sizeof(T) == 8 && NQ == 8;
+        __shared__ T prev_lds[PREV_LDS ? NQ * NT : 1];
+        T prev[PREV_LDS ? 1 : NQ];
+        auto prev_of = [&](int q) -> T { return PREV_LDS ? prev_lds[q * NT + tid] : prev[q]; };
+        for (int x = x0; x <= x1; x++) {
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
 #pragma unroll
                 for (int m = 0; m < 4; m++) w[q][m] = w[q][m + 1];
                 w[q][4] = nw[q];
             }
-            if (x + 1 < x1) fetch(x + 1);
+            if (x < x1) fetch(x + 1);
             // sqrt(rho)-weighted face velocity from cells x-1 (slot 1) and x
             // (slot 2); sqrt(rho) v = m / sqrt(rho), m_y is field 2
             const T rsr = rsqrt_nr(w[0][2]);
             const T vf = (w[2][1] * rsl + w[2][2] * rsr) * rcp_nr(w[0][1] * rsl + w[0][2] * rsr);
             const bool upw = vf >= T(0);
             const T y = upw ? ydx * vf : ydx * (-vf);
-            const int c = base + x * stride;
             T flux[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
@@ -1318,8 +1332,20 @@ struct BAdvFaceMarchY {
                 dmc[q] = dn;
                 fl[q] = fr;
             }
+            if (x > x0) {
+                // cell x - 1: its upper face is face x
+                const int c = base + (x - 1) * stride;
 #pragma unroll
-            for (int q = 0; q < NQ; q++) A.F[q * N + c] = flux[q];
+                for (int q = 0; q < NQ; q++) {
+                    const T d = flux[q] - prev_of(q);
+                    A.F[q * N + c] = d;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                if constexpr (PREV_LDS) prev_lds[q * NT + tid] = flux[q];
+                else prev[q] = flux[q];
+            }
             rsl = rsr;
         }
     }
@@ -1512,7 +1538,7 @@ struct BAdvZUpdate {
             for (int q = 0; q < NQ; q++) {
                 const size_t o = (size_t)(Q0 + q) * N;
                 dx[q] = A.Fx[o + cxp] - A.Fx[o + c];
-                dy[q] = A.Fy[o + cyp] - A.Fy[o + c];
+                dy[q] = A.Fy[o + c];   // the y march stored the difference
                 sv[q] = A.S.f[fld[Q0 + q]][c];
             }
             // the tail's inputs: the first group's new rho and m, the face
@@ -1615,6 +1641,7 @@ struct BAdvXZUpdate {
     static constexpr int NV = own_v ? NQ : NQ + 2;
     static constexpr int RI = own_v ? 0 : NQ;       // staged slot of rho
     static constexpr int MXI = own_v ? 1 : NQ + 1;  // staged slot of mx
+    static constexpr int MINW = (sizeof(T) == 8 && Q0 == 0 && MAXT == 256) ? 3 : 1;
     using Args = AdvXZArgs<T>;
     static __device__ __forceinline__ void run(const Args& A, int blk, int tid)
     {
@@ -1650,7 +1677,6 @@ struct BAdvXZUpdate {
         const T dtdx = T(step_dt(A.a) / A.a.h);
         const int fld[8] = { RHO, MX, MY, MZ, EN, EI, H2, HP };
         const T ra = T(A.rk.a), rb = T(A.rk.b);
-        const int jp = j + 1 == g.ny ? 0 : j + 1;
 
         // window cells z = x0-3 .. x0+2 (slots 0..5); vr, vm: rho and mz of
         // slots 2 and 3 (z-face velocity); vx: mx of slots 2 and 3 (the
@@ -1734,12 +1760,11 @@ struct BAdvXZUpdate {
             // the cell's y flux difference and Runge-Kutta input, loaded
             // before any store
             const int c = base + x * stride;
-            const int cyp = c + (jp - j) * g.nx;
             T dy[NQ], sv[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 const size_t o = (size_t)(Q0 + q) * N;
-                dy[q] = A.Fy[o + cyp] - A.Fy[o + c];
+                dy[q] = A.Fy[o + c];   // the y march stored the difference
                 sv[q] = A.S.f[fld[Q0 + q]][c];
             }
             // x faces of plane x: publish the cell, then its limited slope,
