@@ -257,6 +257,24 @@ def test_fault_flags():
         box.step(-1.0)
 
 
+@pytest.mark.parametrize("precision,slack", [(binding.FP64, 1e-12), (binding.FP32_MIXED, 1e-4)])
+def test_cfl_slack_edges(precision, slack):
+    # an explicit dt is accepted up to the bound times (1 + slack) and latches
+    # MHD_ECFL above it
+    W = inputs.turbulence(16, seed=8, mach=4.0, beta=1.0, x_h2=1e-3)
+    box = binding.Box(W.shape[1:], precision=precision)
+    for factor, ok in ((1.0 + 0.5 * slack, True), (1.0 + 2.0 * slack, False)):
+        box.init_state(W)
+        dt = box.cfl_dt()
+        box.step(dt * factor)
+        if ok:
+            box.cfl_dt()
+        else:
+            with pytest.raises(binding.MhdError) as e:
+                box.cfl_dt()
+            assert e.value.status == binding.MHD_ECFL
+
+
 @pytest.mark.parametrize("recipe", ["c3", "c4"])
 def test_fp32_mixed_against_fp64(recipe):
     # precision form at a small size: totals of the FP32-state path within 1e-5
