@@ -754,6 +754,10 @@ struct BNonadvUpdate {
             Ey_c = T(0.25) * (((ezy[c + dxm] + ezy_c) + exy[zm]) + exy_c);
         }
         const T ra = T(A.rk.a), rb = T(A.rk.b);
+        // two (FP64) or four (FP32) planes per loop trip: the loads of the
+        // later planes are in flight with the earlier planes' arithmetic
+        // (the kernel waits on memory latency, not bandwidth)
+#pragma unroll(sizeof(T) == 8 ? 2 : 4)
         for (int k = k0; k < k1; k++) {
             const int c = i + nx * j + nxy * k;
             const int dzp = ((k + 1 == nz ? 0 : k + 1) - k) * nxy;
