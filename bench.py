@@ -5,25 +5,26 @@
 A step is one full pass of the method over the box: NONADV stage (3 RK
 substages: face Riemann solves along y, z, then x fused with the update of
 m, E, e, then the face-field update from edge fields), ADV stage (3 RK
-substages: face fluxes along x, y, then z fused with the update; the last
-substage's energy-group launch also runs the tail: H2 clamp, FP64
-chemistry, FP64 regularisation, CFL speed) and the CFL reduction.  The
-timed region is K steps, each at the CFL dt the previous step's reduction
-left on the device (mhd_step_cfl; c3's FP32 run replays the dt sequence of
-its FP64 run), with the state resident in HBM, bracketed by device
-synchronisation.
+substages: face fluxes along y, then the update by field group with its x
+faces (exchanged through LDS within whole x rows) and z faces (marched)),
+the tail (H2 clamp, FP64 chemistry, FP64 regularisation, CFL speed) and the
+CFL reduction.  The timed region is K steps, each at the CFL dt the
+previous step's reduction left on the device (mhd_step_cfl), with the state
+resident in HBM, bracketed by device synchronisation.  The FP32 forms'
+errors against their FP64 run come from a second, untimed FP32 run that
+replays the FP64 dt sequence (each dt held to the FP32 state's CFL bound).
 
 Workloads (synthetic, seeded; see paper_1608_08748_amd/inputs.py):
   c2  256^3 FP64, rms Mach 5, beta 1, x_H2 1e-3, seed 2   (default)
   c3  512^3 FP32 state (FP64 chemistry / reductions), rms Mach 5, beta 0.3,
-      seed 3, with the FP64 run of the same seed and dt sequence for the error
+      seed 3, with the FP64 run of the same seed for the error
   c1  32^3 FP64 white-noise box (the oracle's own configuration)
   c4  1024^3 FP32 single box (about 237 GB of HBM), conservation over the run
   c5  serving: 256 boxes of {32..128}^3 with Poisson arrivals, p50/p99 latency
 
 The default line (c2) also carries two legs of the metric: the FP32 form on
-the same 256^3 state and dt sequence with its total and field errors against
-the FP64 run (`fp32_leg`), and the serving workload with p50/p99 latency and
+the same 256^3 state with its total and field errors against the FP64 run
+(`fp32_leg`), and the serving workload with p50/p99 latency and
 served-FP32-vs-FP64 errors for a sample of requests (`serving_leg`);
 --no-legs leaves them out.
 
