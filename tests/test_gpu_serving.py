@@ -219,6 +219,19 @@ def test_persistent_launches_with_uneven_boxes_and_arrivals():
 
 
 def test_persistent_flags_rejected():
+    import ctypes
+    import torch
     for kw in ({"persistent": True, "max_workgroups": -1},):
         with pytest.raises(binding.MhdError):
             binding.Server(1 << 28, max_slots=2, precision=binding.FP32_MIXED, **kw)
+    # a persistent flag other than 0 or 1, through the C ABI
+    p = binding.server_params(precision=binding.FP32_MIXED, max_slots=2)
+    p.persistent = 2
+    total = (1 << 28) + binding.lib().mhd_server_reserved_bytes()
+    ws = torch.empty(total, dtype=torch.uint8, device="cuda")
+    p.stream = torch.cuda.current_stream().cuda_stream
+    p.workspace = ws.data_ptr()
+    p.workspace_bytes = total
+    h = ctypes.c_void_p()
+    assert binding.lib().mhd_server_create(ctypes.byref(p), ctypes.byref(h)) == binding.MHD_EINVAL
+    assert not h.value
