@@ -434,6 +434,33 @@ struct BFaceXRows {
         // the face solve; its fluxes go to slots 8-12 (the slopes there were
         // read before the barrier)
         T out[7];
+        // the update's y and z flux values (per-cell differences when the
+        // marches stored them) and, without EARLY, its m, E, e inputs: loaded
+        // after the face solve, before this thread's stores (outputs may alias
+        // inputs as far as the compiler knows) and, with LOADS_AHEAD, before
+        // the barrier, so their latency overlaps the wait (FP64 rows of 512
+        // cells, held to 128 registers, would spill more: they load after it)
+        constexpr bool DIFF = FluxDiff<T>::v;
+        constexpr bool LOADS_AHEAD = !(sizeof(T) == 8 && MAXT == 512);
+        T fy[5], fz[5], fyp[DIFF ? 1 : 5], fzp[DIFF ? 1 : 5];
+        auto load_update_inputs = [&]() {
+#pragma unroll
+            for (int v = 0; v < 5; v++) {
+                fy[v] = A.Fy[v * N + c];
+                fz[v] = A.Fz[v * N + c];
+                if constexpr (!DIFF) {
+                    fyp[v] = A.Fy[v * N + c + dyp];
+                    fzp[v] = A.Fz[v * N + c + dzp];
+                }
+            }
+            if constexpr (!EARLY) {
+#pragma unroll
+                for (int q = 0; q < 5; q++) {
+                    uc[q] = A.U.f[upd[q]][c];
+                    sc[q] = A.S.f[upd[q]][c];
+                }
+            }
+        };
         if (act) {
             // the left cell's right side (Step 5 of parabola_finish on its
             // edge values and its mean q1)
@@ -448,6 +475,7 @@ struct BFaceXRows {
             // parabola variables 3, 4, 5 are Bt1, Bt2, p
             face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
                        T(A.a.theta * (step_dt(A.a) / A.a.h)), srl, srho, out);
+            if constexpr (LOADS_AHEAD) load_update_inputs();
             A.F[5 * N + c] = out[5];
             A.F[6 * N + c] = out[6];
 #pragma unroll
@@ -455,31 +483,21 @@ struct BFaceXRows {
         }
         __syncthreads();
         if (!act) return;
+        if constexpr (!LOADS_AHEAD) load_update_inputs();
 
-        if constexpr (!EARLY) {
-            // all loads before the first store (outputs may alias inputs as
-            // far as the compiler knows)
-#pragma unroll
-            for (int q = 0; q < 5; q++) {
-                uc[q] = A.U.f[upd[q]][c];
-                sc[q] = A.S.f[upd[q]][c];
-            }
-        }
         // update of m, E, e: flux differences of the x faces (the right
-        // cell's lower face from LDS), y and z faces (memory)
+        // cell's lower face from LDS), y and z faces (loaded above)
         const T dtdx = T(step_dt(A.a) / A.a.h);
-        const T* Fy = A.Fy;
-        const T* Fz = A.Fz;
         T dF[3][5];
 #pragma unroll
         for (int v = 0; v < 5; v++) {
             dF[0][v] = sm[(8 + v) * NT + tr] - out[v];
-            if (FluxDiff<T>::v) {   // the marches stored per-cell differences
-                dF[1][v] = Fy[v * N + c];
-                dF[2][v] = Fz[v * N + c];
+            if constexpr (DIFF) {
+                dF[1][v] = fy[v];
+                dF[2][v] = fz[v];
             } else {
-                dF[1][v] = Fy[v * N + c + dyp] - Fy[v * N + c];
-                dF[2][v] = Fz[v * N + c + dzp] - Fz[v * N + c];
+                dF[1][v] = fyp[v] - fy[v];
+                dF[2][v] = fzp[v] - fz[v];
             }
         }
         T inc[5];
