@@ -629,7 +629,14 @@ struct BFaceMarch {
         // the first slide is slot 1 of the first face)
         T srl = root_nr(w[6][2]);
         fetch(x0);
+        // the face's normal field, loaded one face ahead with the entering
+        // cell (loaded at the face, its latency stood before the face solve);
+        // FP64 with the ionisation network has no registers left for it
+        constexpr bool BN_AHEAD = !ION || sizeof(T) == 4;
+        auto bn_of = [&](int x) { return A.U.f[BX + D][base + (DIFF ? wrapc(x, nd) : x) * stride]; };
+        T bnn = BN_AHEAD ? bn_of(x0) : T(0);
         for (int x = x0; x < xe; x++) {
+            const T bnx = BN_AHEAD ? bnn : bn_of(x);
             T qn[6], gn;
             raw_prim<T, ION>(nr, A.a.gamma, qn, gn);
 #pragma unroll
@@ -643,7 +650,10 @@ struct BFaceMarch {
                 for (int m = 0; m < 4; m++) gw[m] = gw[m + 1];
                 gw[4] = gn;
             }
-            if (x + 1 < xe) fetch(x + 1);
+            if (x + 1 < xe) {
+                fetch(x + 1);
+                if constexpr (BN_AHEAD) bnn = bn_of(x + 1);
+            }
             Side<T> R, Ln;
 #pragma unroll
             for (int v = 0; v < 6; v++) {
@@ -662,7 +672,7 @@ struct BFaceMarch {
             T out[7];
             // left cell x-1 is window slot 1, right cell x is slot 2
             const T srr = root_nr(w[6][2]);
-            face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], A.U.f[BX + D][c], L,
+            face_solve(w[6][1], w[5][1], w[3][1], w[4][1], w[6][2], w[5][2], w[3][2], w[4][2], bnx, L,
                        R, gm, ION ? gw[1] : gm, ION ? gw[2] : gm, ION, ydx, srl, srr, out);
             srl = srr;
             if (!DIFF) {
