@@ -1789,16 +1789,7 @@ struct BAdvXZUpdate {
                 vx[1] = nvx;
             }
             if (x + 1 < x1) fetch(x + 1);
-            // the cell's y flux difference and Runge-Kutta input, loaded
-            // before any store
             const int c = base + x * stride;
-            T dy[NQ], sv[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; q++) {
-                const size_t o = (size_t)(Q0 + q) * N;
-                dy[q] = A.Fy[o + c];   // the y march stored the difference
-                sv[q] = A.S.f[fld[Q0 + q]][c];
-            }
             // x faces of plane x: publish the cell, then its limited slope,
             // form the flux of its lower x face, exchange the fluxes
             T* vb = sm + (x & 1) * ((NV + 2 * NQ) * NT);
@@ -1848,6 +1839,19 @@ struct BAdvXZUpdate {
                 }
             }
             __syncthreads();
+            // the cell's y flux difference and Runge-Kutta input: loaded here,
+            // before this plane's stores, so the z flux below hides their
+            // latency; loaded at the top of the plane they lived through the
+            // x faces and cost the registers of a third wave per SIMD (the
+            // first FP64 group then spilled, and the reload of a spilled
+            // address waited for the previous plane's stores)
+            T dy[NQ], sv[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                const size_t o = (size_t)(Q0 + q) * N;
+                dy[q] = A.Fy[o + c];   // the y march stored the difference
+                sv[q] = A.S.f[fld[Q0 + q]][c];
+            }
             // upper face of cell x along z: between slots 2 and 3
             T Fup[NQ], nv[NQ];
             BAdvZUpdate<T, Q0, NQ>::zflux(w, velocity(), ydx, pR, pdq, p6, d1, f1, Fup);
