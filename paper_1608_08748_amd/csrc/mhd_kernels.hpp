@@ -791,6 +791,21 @@ struct BNonadvUpdate {
             const int dzp = ((k + 1 == nz ? 0 : k + 1) - k) * nxy;
             const int dzm = ((k == 0 ? nz - 1 : k - 1) - k) * nxy;
             const int xp = c + dxp, xm = c + dxm, yp = c + dyp, ym = c + dym, zp = c + dzp;
+            constexpr int Q0 = FULL ? 0 : 5;
+            const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
+            // the face fields' Runge-Kutta inputs, all loaded before the
+            // plane's stores (a load issued after a store waits for the store
+            // as well: one memory counter, in order); the full update, with
+            // eight fields, keeps them at the combination (here it would
+            // spill)
+            T uo[8], so[8];
+            if (!FULL && !A.dbg) {
+#pragma unroll
+                for (int q = Q0; q < 8; q++) {
+                    uo[q] = A.U.f[upd[q]][c];
+                    so[q] = A.S.f[upd[q]][c];
+                }
+            }
             T inc[NF];
             if (FULL) {
                 T dF[3][5], fzp[5];
@@ -855,8 +870,6 @@ struct BNonadvUpdate {
             inc[BY] = -dtdx * (Ex_zp - Ex_c) + dtdx * (Ez_xp - Ez_c);
             inc[BZ] = -dtdx * (Ey_xp - Ey_c) + dtdx * (Ex_yp - Ex_c);
 
-            constexpr int Q0 = FULL ? 0 : 5;
-            const int upd[8] = { MX, MY, MZ, EN, EI, BX, BY, BZ };
             if (A.dbg) {
 #pragma unroll
                 for (int q = Q0; q < 8; q++) A.O.f[upd[q]][c] = inc[upd[q]];
@@ -868,9 +881,11 @@ struct BNonadvUpdate {
             } else {
 #pragma unroll
                 for (int q = Q0; q < 8; q++) {
-                    int f = upd[q];
-                    T u = A.U.f[f][c];
-                    A.O.f[f][c] = (u + ra * (A.S.f[f][c] - u)) + rb * inc[f];
+                    if constexpr (FULL) {
+                        uo[q] = A.U.f[upd[q]][c];
+                        so[q] = A.S.f[upd[q]][c];
+                    }
+                    A.O.f[upd[q]][c] = (uo[q] + ra * (so[q] - uo[q])) + rb * inc[upd[q]];
                 }
             }
             Ex_c = Ex_zp;
