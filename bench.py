@@ -143,7 +143,7 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 TRAFFIC = {
     # average of the x-row (with the m, E, e update), y-march and z-march
     # face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("3893ceab0531a400", 3127439911),
+    ("c2", 8, "nonadv_face"): ("7a0934bea43b1000", 3127511694),
 }
 
 
