@@ -341,9 +341,30 @@ struct BFaceXRows {
         const size_t N = (size_t)g.n;
         const int nx = g.nx;
         check_dt(A, blk, tid);
-        int r = tid / nx;
-        int i = tid - r * nx;
-        int row = blk * A.rpb + r;
+        // row r of the block, cell i of the row (one row per block: no
+        // per-thread division)
+        int r, i;
+        if (nx == NT) {
+            r = 0;
+            i = tid;
+        } else {
+            r = tid / nx;
+            i = tid - r * nx;
+        }
+        const int row = blk * A.rpb + r;
+        // the row's y and z indices: with rows of a multiple of 64 cells each
+        // wave lies in one row and divides once, on the scalar unit (unsigned
+        // there, so that the compiler does not merge the two divisions into
+        // one per-thread division after the branch)
+        int j, k;
+        if ((nx & 63) == 0) {
+            const unsigned wrow = (unsigned)__builtin_amdgcn_readfirstlane(row);
+            j = (int)(wrow % (unsigned)g.ny);
+            k = (int)(wrow / (unsigned)g.ny);
+        } else {
+            j = row % g.ny;
+            k = row / g.ny;
+        }
         bool act = r < A.rpb && row < g.ny * g.nz;
         const int rowbase = row * nx;
         const int c = rowbase + i;
@@ -353,9 +374,16 @@ struct BFaceXRows {
         const int tm2 = rb + wrapc(i - 2, nx), tp2 = rb + wrapc(i + 2, nx);
         const T gm = T(A.a.gamma);
         // periodic offsets of the upper neighbours along y and z
-        const int j = row % g.ny, k = row / g.ny;
         const int dyp = ((j + 1 == g.ny ? 0 : j + 1) - j) * nx;
         const int dzp = ((k + 1 == g.nz ? 0 : k + 1) - k) * g.nxy;
+        // the step's dt (device-resident under the CFL step), read before any
+        // store of this kernel: read later, each wave would wait for the load
+        // after a barrier, with every other wave of the block (FP64 rows of
+        // 512 cells, held to 128 registers, read it where it is used: the
+        // two registers would spill)
+        constexpr bool DT_EARLY = !(sizeof(T) == 8 && MAXT == 512);
+        const double dt_early = DT_EARLY ? step_dt(A.a) : 0.0;
+        auto dt_now = [&]() { return DT_EARLY ? dt_early : step_dt(A.a); };
 
         // own cell: conserved values, primitives
         // uc, sc: the cell's m, E, e at the substage input and at the stage
@@ -474,7 +502,7 @@ struct BFaceXRows {
             }
             // parabola variables 3, 4, 5 are Bt1, Bt2, p
             face_solve(rl, q1[5], q1[3], q1[4], rho, q2[5], q2[3], q2[4], bn, L, R, gm, gl, gam, ION,
-                       T(A.a.theta * (step_dt(A.a) / A.a.h)), srl, srho, out);
+                       T(A.a.theta * (dt_now() / A.a.h)), srl, srho, out);
             if constexpr (LOADS_AHEAD) load_update_inputs();
             A.F[5 * N + c] = out[5];
             A.F[6 * N + c] = out[6];
@@ -487,7 +515,7 @@ struct BFaceXRows {
 
         // update of m, E, e: flux differences of the x faces (the right
         // cell's lower face from LDS), y and z faces (loaded above)
-        const T dtdx = T(step_dt(A.a) / A.a.h);
+        const T dtdx = T(dt_now() / A.a.h);
         T dF[3][5];
 #pragma unroll
         for (int v = 0; v < 5; v++) {
@@ -515,7 +543,7 @@ struct BFaceXRows {
             // m and -m . grad(Phi) on E, central differences
             const T* ph = A.phi;
             const T i2h = T(0.5 / A.a.h);
-            const T dt = T(step_dt(A.a));
+            const T dt = T(dt_now());
             const int dxp = tr - tid, dxm = tl - tid;
             const int dym = ((j == 0 ? g.ny - 1 : j - 1) - j) * nx;
             const int dzm = ((k == 0 ? g.nz - 1 : k - 1) - k) * g.nxy;
