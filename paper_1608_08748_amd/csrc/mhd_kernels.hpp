@@ -1953,7 +1953,18 @@ struct BTail {
         double spd = 0.0;
         if (c < g.n) {
             int i, j, k;
-            decompose(g, c, i, j, k);
+            if ((g.nx & 63) == 0) {
+                // every wave lies in one x row: its row is divided once, on
+                // the scalar unit (signed there, so that the compiler does
+                // not merge it with the per-thread division below)
+                const int c0 = __builtin_amdgcn_readfirstlane(c);
+                const int row = c0 / g.nx;
+                j = row % g.ny;
+                k = row / g.ny;
+                i = (c0 - row * g.nx) + (c - c0);
+            } else {
+                decompose(g, c, i, j, k);
+            }
             const Fields<T>& U = A.U;
             double rho = (double)U.f[RHO][c];
             double mx = (double)U.f[MX][c], my = (double)U.f[MY][c], mz = (double)U.f[MZ][c];
