@@ -41,6 +41,24 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// XCD bands: a launch whose logical blocks are L = (s * nb + y) * ni + i
+// (i < ni fastest, then y < nb, then s) deals y in eight contiguous bands, one
+// per XCD, over every s: at any moment the eight XCDs work on the same s at
+// bands nb / 8 apart, and the neighbours at y +- 1 and s + 1 of a block mostly
+// ran on its own XCD shortly before or after it, so their reads hit its L2
+// (a single contiguous range per XCD makes the XCDs stream from places far
+// apart in memory at once, which was slower).  Identity unless 8 divides nb
+// and the grid holds exactly ni * nb * ns blocks (a multi-box launch holds
+// more, a resident one fewer); a bijection of [0, ni * nb * ns) either way.
+__device__ __forceinline__ int xcd_band(int b, int ni, int nb, int ns)
+{
+    if (nb % 8 != 0 || (int)gridDim.x != ni * nb * ns) return b;
+    const int per = ni * (nb / 8);   // blocks of one band and one s
+    const int x = b % 8, q = b / 8;
+    const int s = q / per, l = q - s * per;
+    return (s * nb + x * (nb / 8) + l / ni) * ni + l % ni;
+}
+
 // kernels whose stencil spans neighbouring rows of other blocks opt in with
 // `static constexpr bool XCD = true`
 template <class Body>
@@ -341,6 +359,10 @@ struct BFaceXRows {
         const size_t N = (size_t)g.n;
         const int nx = g.nx;
         check_dt(A, blk, tid);
+        // one row per block: rows in XCD bands, so the next row's and the next
+        // plane's y and z fluxes are mostly read through this XCD's L2 (a fifth
+        // of the reads fewer, about 1% slower)
+        blk = xcd_band(blk, 1, g.ny, g.nz);
         // row r of the block, cell i of the row (one row per block: no
         // per-thread division)
         int r, i;
@@ -764,6 +786,10 @@ struct BNonadvUpdate {
         const Geo& g = A.g;
         const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy;
         int i, j, k0, k1;
+        // the y-neighbour rows at the tile edges and the z-neighbour
+        // segment are read through the same L2 (a quarter of the reads
+        // fewer, 2% faster)
+        blk = xcd_band(blk, A.zt.ntx, A.zt.nty, (g.nz + A.zt.seg - 1) / A.zt.seg);
         if (!ztile_cell(g, A.zt, blk, tid, i, j, k0, k1)) return;
         const size_t N = (size_t)g.n;
         const T dtdx = T(step_dt(A.a) / A.a.h);
