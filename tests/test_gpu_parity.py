@@ -108,13 +108,15 @@ def test_ragged_non_cubic_box():
 
 
 @pytest.mark.parametrize("shape", [(3, 2, 300), (2, 3, 520), (5, 40, 1), (40, 1, 3), (5, 7, 64), (3, 5, 128),
-                                   (2, 3, 192), (2, 3, 256)])
+                                   (2, 3, 192), (2, 3, 256), (2, 8, 256), (2, 32, 64)])
 def test_face_kernel_dispatch_paths(shape):
     # x rows longer than one 256-thread block, rows beyond the FP64 row-block
     # limit (one face per thread), lines shorter than the marching segment;
     # rows of a multiple of 64 cells (row indices taken once per wave in the
     # x-row and tail kernels), four or two of them per block, one shorter
-    # than its block and one that fills it
+    # than its block and one that fills it; blocks renumbered in XCD bands
+    # (x rows of 256 cells, 8 rows per plane; face-field update tiles, 8 tile
+    # rows per plane)
     W = inputs.white_noise(shape, seed=27, sigma=0.3, B=(0.2, -0.3, 0.1))
     box, P, U = _pair(W)
     for _ in range(2):
