@@ -49,7 +49,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 // (a single contiguous range per XCD makes the XCDs stream from places far
 // apart in memory at once, which was slower).  Identity unless 8 divides nb
 // and the grid holds exactly ni * nb * ns blocks (a multi-box launch holds
-// more, a resident one fewer); a bijection of [0, ni * nb * ns) either way.
+// more, a resident one fewer); a bijection of [0, ni * nb * ns) either way,
+// so the caller's logical blocks must be exactly that range.
 __device__ __forceinline__ int xcd_band(int b, int ni, int nb, int ns)
 {
     if (nb % 8 != 0 || (int)gridDim.x != ni * nb * ns) return b;
@@ -361,8 +362,10 @@ struct BFaceXRows {
         check_dt(A, blk, tid);
         // one row per block: rows in XCD bands, so the next row's and the next
         // plane's y and z fluxes are mostly read through this XCD's L2 (a fifth
-        // of the reads fewer, about 1% slower)
-        blk = xcd_band(blk, 1, g.ny, g.nz);
+        // of the reads fewer, about 1% slower).  Only then are the row indices
+        // the block indices: with several rows per block the band's domain
+        // (ny nz) would exceed the blocks
+        if (A.rpb == 1) blk = xcd_band(blk, 1, g.ny, g.nz);
         // row r of the block, cell i of the row (one row per block: no
         // per-thread division)
         int r, i;

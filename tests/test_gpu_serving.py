@@ -50,6 +50,24 @@ def test_alone_equals_mix_equals_single_box(precision):
         np.testing.assert_array_equal(box.totals(), mix["records"][i]["totals"])
 
 
+def test_merged_launch_with_a_grid_of_another_boxs_row_count():
+    # A (32^3: 8 rows of 32 cells per x-row block, 128 blocks for 1024 rows)
+    # and B (256-cell rows, 896 blocks) in one merged FP32 launch of 1024
+    # workgroups, the row count of A: the XCD-band renumbering of the x rows
+    # applies to one-row-per-block boxes only, so A's blocks stay its own
+    A = inputs.turbulence(32, seed=51, mach=3.0, beta=1.0, x_h2=1e-3)
+    B = inputs.white_noise((32, 28, 256), seed=52, sigma=0.3, B=(0.2, -0.1, 0.1))
+    mix, mix_res = _serve([A, B], binding.FP32_MIXED)
+    assert mix["max_active"] == 2
+    for i, W in enumerate([A, B]):
+        box = binding.Box(W.shape[1:], precision=binding.FP32_MIXED)
+        box.init_state(W)
+        for _ in range(3):
+            box.step_cfl()
+        np.testing.assert_array_equal(box.get_state(), mix_res[i])
+        box.close()
+
+
 def test_budget_limits_boxes_in_flight():
     states = [inputs.turbulence(16, seed=40 + k, mach=2.0, beta=1.0, x_h2=1e-3) for k in range(6)]
     p = binding.server_params(precision=binding.FP32_MIXED)
