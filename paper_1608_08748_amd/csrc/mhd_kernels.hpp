@@ -1855,7 +1855,7 @@ struct BAdvXZUpdate {
             }
         };
         fetch(x0);
-        for (int x = x0; x < x1; x++) {
+        auto plane = [&](int x) {
             // slide: window slots 0..5 = cells x-2 .. x+3
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
@@ -1963,7 +1963,20 @@ struct BAdvXZUpdate {
                     A.O.f[BZ][c] = T(0);
                 }
             }
+        };
+        // FP32 groups without the H+ field take two planes per loop trip: the
+        // window and the carried z-face values are renamed instead of moved
+        // (four waves per SIMD instead of five; 7% faster at 512 and 1024
+        // cells per row, level at 256).  FP64 and the H+ group keep one.
+        int x = x0;
+        if constexpr (sizeof(T) == 4 && Q0 + NQ <= 7) {
+            for (; x + 1 < x1; x += 2) {
+                plane(x);
+                __builtin_amdgcn_sched_barrier(0);
+                plane(x + 1);
+            }
         }
+        for (; x < x1; x++) plane(x);
     }
 };
 
