@@ -143,7 +143,7 @@ VALU_PEAK_TF = {8: 78.6, 4: 157.3}
 TRAFFIC = {
     # average of the x-row (with the m, E, e update), y-march and z-march
     # face kernels, bytes per launch
-    ("c2", 8, "nonadv_face"): ("064e6c26d774836b", 2867909099),
+    ("c2", 8, "nonadv_face"): ("2f1f983544ad1a06", 2868160284),
 }
 
 
